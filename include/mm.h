@@ -1,0 +1,168 @@
+/*
+ * mm.h -- C ABI of the MI355X (gfx950) micromagnetic step library.
+ *
+ * The library evaluates the effective field of Zhu, "Grace: a Cross-platform
+ * Micromagnetic Simulator On Graphics Processing Units" (arXiv:1411.2565),
+ * Sec. 2 eq. (2):
+ *     H_eff = H_exch + H_anis + H_demag + H_extern,
+ * with the demagnetising field computed as the zero-padded FFT convolution of
+ * the magnetisation with the cell-averaged demag tensor (Sec. 3), the exchange
+ * field with the six-neighbour scheme (Sec. 3), and advances the magnetisation
+ * with the explicit-Euler integration of the LLG equation, eq. (3) (Sec. 3).
+ *
+ * Conventions shared by every call:
+ *   - Units are SI: lengths m, fields and Ms A/m, A J/m, Ku J/m^3, dt s,
+ *     gamma0 = gamma*mu0 in m/(A s).  mu0 = 4 pi 1e-7 exactly.
+ *   - The state is the unit magnetisation m, FP32, structure of arrays
+ *     [3][nz][ny][nx] with x fastest, in device memory.  Per-cell scalar maps
+ *     are [nz][ny][nx].
+ *   - Every device pointer is owned by the caller, must be 16-byte aligned
+ *     and must stay valid until the work enqueued on the context's stream has
+ *     finished.  The library keeps no pointer to caller arrays after a call
+ *     returns, except the workspace given to mm_set_workspace.
+ *   - The library allocates no device memory.  All scratch lives in one
+ *     caller-provided workspace (mm_workspace_size / mm_set_workspace).
+ *   - Calls enqueue on the context's HIP stream and return without waiting,
+ *     except mm_create, mm_build_tensor and mm_sync, which synchronise.
+ *     Argument checks are synchronous and happen on the host before any
+ *     work is enqueued; a rejected call enqueues nothing.
+ *   - Errors are negative mm_status codes; mm_last_error returns a message
+ *     for the most recent failure on that context.  No C++ exception
+ *     crosses this interface.  A context is not thread-safe.
+ *   - Supported sizes: 2 <= nx <= 512, 1 <= ny <= 512, 1 <= nz <= 512.
+ *     Each axis with n > 1 is zero-padded to the smallest power of two
+ *     P >= 2n - 1 (an axis with n = 1 is not padded); any such P gives the
+ *     same linear convolution.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MM_OK = 0,
+    MM_EINVAL = -1,      /* invalid argument (size, pointer, value) */
+    MM_ESTATE = -2,      /* call out of order (no workspace, material or tensor) */
+    MM_ENOMEM = -3,      /* workspace too small */
+    MM_EHIP = -4,        /* a HIP runtime call failed */
+    MM_EUNSUP = -5,      /* supported by the method but not by this build */
+    MM_ENONFINITE = -6   /* a step produced a non-finite magnetisation */
+} mm_status;
+
+typedef struct mm_ctx mm_ctx;
+
+/* Grid of nx*ny*nz rectangular cells of size dx*dy*dz (Sec. 2, and the
+ * "-rectang" record of the paper's input file, Sec. 5). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;
+} mm_geometry;
+
+/* Material of Sec. 2: Ms (uniform; see mm_set_ms_map for a map), exchange
+ * stiffness A, uniaxial anisotropy constant Ku along the unit axis u (the
+ * paper's anisotropy field H_K corresponds to Ku = mu0 Ms H_K / 2), damping
+ * alpha and gamma0 = gamma*mu0 of eq. (3). */
+typedef struct {
+    double Ms, A, Ku, u[3], alpha, gamma0;
+} mm_material;
+
+/* Field terms of eq. (2). */
+enum { MM_T_EXCH = 1, MM_T_DEMAG = 2, MM_T_ANIS = 4, MM_T_ZEEMAN = 8, MM_T_ALL = 15 };
+
+/* Step flags. */
+enum {
+    MM_F_NO_RENORM = 1,    /* skip m <- m/|m| after each Euler step */
+    MM_F_COMPENSATED = 2   /* compensated (Dot2) FP32 spectral tensor multiply */
+};
+
+/* Create a context for a geometry on HIP device `device`; work is enqueued
+ * on `hip_stream` (a hipStream_t, NULL = the device's null stream).  Checks
+ * the sizes, fixes the padded FFT sizes and prepares the device-side
+ * constant tables (synchronous).  *out receives the context. */
+mm_status mm_create(mm_ctx **out, const mm_geometry *g, int device, void *hip_stream);
+
+/* Destroy a context (does not free the caller's workspace). */
+mm_status mm_destroy(mm_ctx *c);
+
+/* Change the stream subsequent calls enqueue on. */
+mm_status mm_set_stream(mm_ctx *c, void *hip_stream);
+
+/* Bytes of device workspace the context needs (for the tensor spectrum,
+ * FFT intermediates, the second state buffer, maps and reduction partials). */
+mm_status mm_workspace_size(const mm_ctx *c, size_t *bytes);
+
+/* Hand the context a caller-owned device buffer of at least
+ * mm_workspace_size bytes, 256-byte aligned.  The tensor spectrum and the
+ * copied maps live in it, so replacing the workspace requires calling
+ * mm_build_tensor (and the map setters) again. */
+mm_status mm_set_workspace(mm_ctx *c, void *dev_ptr, size_t bytes);
+
+/* Set the material (Sec. 2; eq. (3) for alpha and gamma0).  Requires
+ * Ms > 0, A >= 0, Ku >= 0, |u| > 0 (normalised here), alpha >= 0,
+ * gamma0 > 0. */
+mm_status mm_set_material(mm_ctx *c, const mm_material *mat);
+
+/* Per-cell saturation magnetisation map (N floats, device, all > 0), copied
+ * into the workspace on the stream; NULL returns to the uniform Ms. */
+mm_status mm_set_ms_map(mm_ctx *c, const float *ms_dev);
+
+/* Uniform external field (Sec. 2, H_extern), A/m. */
+mm_status mm_set_hext(mm_ctx *c, const double h[3]);
+
+/* Per-cell external field map (3N floats [3][nz][ny][nx], device, A/m),
+ * copied into the workspace on the stream; NULL returns to the uniform
+ * field. */
+mm_status mm_set_hext_map(mm_ctx *c, const float *h_dev);
+
+/* Build the demag tensor spectrum for the geometry (Sec. 3: the convolution
+ * kernel of the zero-padded FFT evaluation).  The cell-averaged tensor is
+ * evaluated in FP64 on the GPU (Newell's closed form near the source, a
+ * tent-weighted Gauss-Legendre quadrature of the dipole kernel far from it),
+ * transformed in FP64 and stored as FP32.  Needs the workspace; overwrites
+ * the FFT intermediates.  Synchronous. */
+mm_status mm_build_tensor(mm_ctx *c);
+
+/* Diagnostic: write the FP64 real-space tensor for the non-negative octant
+ * of cell offsets, [6][nz][ny][nx] in the order xx, yy, zz, xy, xz, yz,
+ * into tab_dev (6N doubles, device).  Synchronous. */
+mm_status mm_tensor_table(mm_ctx *c, double *tab_dev);
+
+/* Effective field of eq. (2) restricted to the terms in `terms`
+ * (MM_T_* mask) for the state m_dev, written to h_dev (3N floats, A/m,
+ * may not alias m_dev).  MM_T_DEMAG requires mm_build_tensor. */
+mm_status mm_compute_heff(mm_ctx *c, const float *m_dev, float *h_dev, uint32_t terms);
+
+/* Advance m_dev in place by nsteps explicit-Euler steps of eq. (3) with all
+ * four field terms:
+ *     m <- m + dt * (-gamma0/(1+alpha^2)) [m x H + alpha m x (m x H)],
+ * followed by m <- m/|m| unless MM_F_NO_RENORM.  dt > 0, nsteps >= 0. */
+mm_status mm_step_llg(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32_t flags);
+
+/* FP64 reductions of the energy of eq. (1) summed over cells and of the
+ * mean magnetisation, written to out_dev (8 doubles, device):
+ *     E_exch, E_demag, E_anis, E_zeeman, E_total, <mx>, <my>, <mz>  (J, -).
+ * Terms follow the paper's energy density with the cell volume V:
+ *     E_exch  = A V sum over neighbour pairs |m_j - m_i|^2 / d^2
+ *     E_demag = -(mu0 V / 2) sum Ms m . H_demag
+ *     E_anis  = Ku V sum (1 - (m . u)^2)
+ *     E_zeeman = -mu0 V sum Ms m . h_ext */
+mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
+
+/* Wait for the context's stream; report a HIP error or a non-finite state
+ * flagged by an earlier step (MM_ENONFINITE, flag cleared on report). */
+mm_status mm_sync(mm_ctx *c);
+
+/* Message for the last failure on this context ("" if none).  The pointer
+ * stays valid until the next call on the context. */
+const char *mm_last_error(const mm_ctx *c);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

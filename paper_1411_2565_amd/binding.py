@@ -1,0 +1,272 @@
+"""Python binding of the C ABI in ``include/mm.h`` (argument marshalling only).
+
+Each ``mm_*`` function here has the name and meaning of the C entry point it
+wraps; device memory is passed as torch CUDA (HIP) tensors, and work is
+enqueued on torch's current stream.  Every computation runs in the HIP
+kernels of ``libmm.so``; if the library is missing this module raises instead
+of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+from . import build as _build
+
+MM_OK, MM_EINVAL, MM_ESTATE, MM_ENOMEM, MM_EHIP, MM_EUNSUP, MM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+MM_T_EXCH, MM_T_DEMAG, MM_T_ANIS, MM_T_ZEEMAN, MM_T_ALL = 1, 2, 4, 8, 15
+MM_F_NO_RENORM, MM_F_COMPENSATED = 1, 2
+
+_NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ESTATE", -3: "MM_ENOMEM", -4: "MM_EHIP",
+          -5: "MM_EUNSUP", -6: "MM_ENONFINITE"}
+
+
+class mm_geometry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class mm_material(ctypes.Structure):
+    _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("Ku", ctypes.c_double),
+                ("u", ctypes.c_double * 3), ("alpha", ctypes.c_double), ("gamma0", ctypes.c_double)]
+
+
+class MMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+_P = ctypes.c_void_p
+
+
+def load():
+    """Load libmm.so from the package directory (built by ``build.build()``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = _build.library_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    st = ctypes.c_int
+    sig = {
+        "mm_create": [ctypes.POINTER(_P), ctypes.POINTER(mm_geometry), ctypes.c_int, _P],
+        "mm_destroy": [_P],
+        "mm_set_stream": [_P, _P],
+        "mm_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
+        "mm_set_workspace": [_P, _P, ctypes.c_size_t],
+        "mm_set_material": [_P, ctypes.POINTER(mm_material)],
+        "mm_set_ms_map": [_P, _P],
+        "mm_set_hext": [_P, ctypes.POINTER(ctypes.c_double)],
+        "mm_set_hext_map": [_P, _P],
+        "mm_build_tensor": [_P],
+        "mm_tensor_table": [_P, _P],
+        "mm_compute_heff": [_P, _P, _P, ctypes.c_uint32],
+        "mm_step_llg": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32],
+        "mm_reduce": [_P, _P, _P],
+        "mm_sync": [_P],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = st
+    L.mm_last_error.argtypes = [_P]
+    L.mm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def mm_last_error(ctx) -> str:
+    return load().mm_last_error(ctx).decode()
+
+
+def _check(ctx, status, what):
+    if status != MM_OK:
+        msg = mm_last_error(ctx) if ctx else ""
+        raise MMError(status, f"{what}: {msg}")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, numel, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of {numel} elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ C names
+
+def mm_create(n, d, device=0, stream=None):
+    g = mm_geometry(int(n[0]), int(n[1]), int(n[2]), float(d[0]), float(d[1]), float(d[2]))
+    ctx = _P()
+    s = stream if stream is not None else _stream()
+    _check(None, load().mm_create(ctypes.byref(ctx), ctypes.byref(g), int(device), s), "mm_create")
+    return ctx
+
+
+def mm_destroy(ctx):
+    _check(None, load().mm_destroy(ctx), "mm_destroy")
+
+
+def mm_set_stream(ctx, stream=None):
+    _check(ctx, load().mm_set_stream(ctx, stream if stream is not None else _stream()), "mm_set_stream")
+
+
+def mm_workspace_size(ctx) -> int:
+    b = ctypes.c_size_t()
+    _check(ctx, load().mm_workspace_size(ctx, ctypes.byref(b)), "mm_workspace_size")
+    return b.value
+
+
+def mm_set_workspace(ctx, ws):
+    _check(ctx, load().mm_set_workspace(ctx, ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
+           "mm_set_workspace")
+
+
+def mm_set_material(ctx, Ms, A, Ku=0.0, u=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5):
+    m = mm_material(float(Ms), float(A), float(Ku), (ctypes.c_double * 3)(*map(float, u)),
+                    float(alpha), float(gamma0))
+    _check(ctx, load().mm_set_material(ctx, ctypes.byref(m)), "mm_set_material")
+
+
+def mm_set_ms_map(ctx, ms, N=None):
+    import torch
+    p = None if ms is None else _dev(ms, torch.float32, N if N is not None else ms.numel(), "ms map")
+    _check(ctx, load().mm_set_ms_map(ctx, p), "mm_set_ms_map")
+
+
+def mm_set_hext(ctx, h):
+    arr = (ctypes.c_double * 3)(*map(float, h))
+    _check(ctx, load().mm_set_hext(ctx, arr), "mm_set_hext")
+
+
+def mm_set_hext_map(ctx, h, N=None):
+    import torch
+    p = None if h is None else _dev(h, torch.float32, 3 * N if N is not None else h.numel(), "field map")
+    _check(ctx, load().mm_set_hext_map(ctx, p), "mm_set_hext_map")
+
+
+def mm_build_tensor(ctx):
+    _check(ctx, load().mm_build_tensor(ctx), "mm_build_tensor")
+
+
+def mm_tensor_table(ctx, out, N):
+    import torch
+    _check(ctx, load().mm_tensor_table(ctx, _dev(out, torch.float64, 6 * N, "table")), "mm_tensor_table")
+
+
+def mm_compute_heff(ctx, m, h, terms, N):
+    import torch
+    _check(ctx, load().mm_compute_heff(ctx, _dev(m, torch.float32, 3 * N, "m"),
+                                       _dev(h, torch.float32, 3 * N, "h"), int(terms)), "mm_compute_heff")
+
+
+def mm_step_llg(ctx, m, nsteps, dt, flags, N):
+    import torch
+    _check(ctx, load().mm_step_llg(ctx, _dev(m, torch.float32, 3 * N, "m"), int(nsteps), float(dt), int(flags)),
+           "mm_step_llg")
+
+
+def mm_reduce(ctx, m, out, N):
+    import torch
+    _check(ctx, load().mm_reduce(ctx, _dev(m, torch.float32, 3 * N, "m"), _dev(out, torch.float64, 8, "out")),
+           "mm_reduce")
+
+
+def mm_sync(ctx):
+    _check(ctx, load().mm_sync(ctx), "mm_sync")
+
+
+# -------------------------------------------------------------- convenience
+
+class Sim:
+    """One sample on one GPU: owns the context and a torch workspace tensor.
+
+    ``Sim(n, d, Ms=..., A=..., ...)`` creates the context, sets the material,
+    hands over the workspace and builds the tensor spectrum.  Methods enqueue
+    on torch's current stream."""
+
+    def __init__(self, n, d, Ms, A, Ku=0.0, u=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5,
+                 hext=(0.0, 0.0, 0.0), device=0, build_tensor=True):
+        import torch
+        self.n, self.d = tuple(int(v) for v in n), tuple(float(v) for v in d)
+        self.N = self.n[0] * self.n[1] * self.n[2]
+        self.device = torch.device("cuda", device)
+        with torch.cuda.device(self.device):
+            self.ctx = mm_create(self.n, self.d, device)
+            nbytes = mm_workspace_size(self.ctx)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            self._ws_view = self.ws[off:off + nbytes]
+            mm_set_workspace(self.ctx, self._ws_view)
+            mm_set_material(self.ctx, Ms, A, Ku, u, alpha, gamma0)
+            mm_set_hext(self.ctx, hext)
+            if build_tensor:
+                mm_build_tensor(self.ctx)
+
+    @property
+    def shape(self):
+        nx, ny, nz = self.n
+        return (3, nz, ny, nx)
+
+    def _s(self):
+        mm_set_stream(self.ctx)
+
+    def heff(self, m, terms=MM_T_ALL):
+        import torch
+        self._s()
+        h = torch.empty(self.shape, dtype=torch.float32, device=self.device)
+        mm_compute_heff(self.ctx, m, h, terms, self.N)
+        return h
+
+    def step(self, m, nsteps, dt, flags=0):
+        self._s()
+        mm_step_llg(self.ctx, m, nsteps, dt, flags, self.N)
+        return m
+
+    def reduce(self, m):
+        import torch
+        self._s()
+        out = torch.empty(8, dtype=torch.float64, device=self.device)
+        mm_reduce(self.ctx, m, out, self.N)
+        return out
+
+    def tensor_table(self):
+        import torch
+        self._s()
+        out = torch.empty((6,) + self.shape[1:], dtype=torch.float64, device=self.device)
+        mm_tensor_table(self.ctx, out, self.N)
+        return out
+
+    def set_ms_map(self, ms):
+        self._s()
+        mm_set_ms_map(self.ctx, ms, self.N)
+
+    def set_hext_map(self, h):
+        self._s()
+        mm_set_hext_map(self.ctx, h, self.N)
+
+    def set_hext(self, h):
+        mm_set_hext(self.ctx, h)
+
+    def sync(self):
+        mm_sync(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            mm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

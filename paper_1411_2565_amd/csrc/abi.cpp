@@ -1,0 +1,450 @@
+// abi.cpp -- the C ABI of include/mm.h: argument checks, padded sizes,
+// workspace carving and the order of kernel launches for one step.
+//
+// Paper: Zhu, "Grace" (arXiv:1411.2565).  Sec. 3: every step evaluates the
+// demagnetising field by zero-padded FFT convolution, adds the six-neighbour
+// exchange field, anisotropy and external field, and applies one explicit
+// Euler step of eq. (3); the data stays on the GPU between steps and only
+// the caller's explicit reads cross to the host.
+#include "mm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "launch.hpp"
+
+namespace {
+
+constexpr double kMu0 = 4.0e-7 * M_PI;
+constexpr int kMaxN = 512;
+
+struct Carve {
+    size_t off = 0;
+    size_t take(size_t bytes)
+    {
+        const size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    }
+};
+
+}  // namespace
+
+struct mm_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    mmk::Geo g{};
+    double d[3] = {0, 0, 0};
+    mm_material mat{};
+    bool have_mat = false;
+    double hext[3] = {0, 0, 0};
+    bool ms_map = false, h_map = false, tensor = false;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    // workspace layout (byte offsets)
+    size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_T = 0, o_tA = 0, o_tB = 0;
+    size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, total = 0;
+    std::string err;
+
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+mm_status fail(mm_ctx *c, mm_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+mm_status hipcheck(mm_ctx *c, hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return fail(c, MM_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return MM_OK;
+}
+
+#define MM_TRY(expr)                        \
+    do {                                    \
+        mm_status _s = (expr);              \
+        if (_s != MM_OK) return _s;         \
+    } while (0)
+
+int padded(int n)
+{
+    if (n == 1) return 1;
+    int p = 1;
+    while (p < 2 * n - 1) p *= 2;
+    return p;
+}
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+std::mutex g_init_mu;
+bool g_init_done[64] = {false};
+
+// device tables (twiddles) once per device, with that device current
+mm_status init_device(mm_ctx *c)
+{
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (c->device < 0 || c->device >= 64) return fail(c, MM_EINVAL, "device index %d out of range", c->device);
+    if (g_init_done[c->device]) return MM_OK;
+    MM_TRY(hipcheck(c, mmk::init_tables(c->stream), "init_tables"));
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "init_tables sync"));
+    g_init_done[c->device] = true;
+    return MM_OK;
+}
+
+void layout(mm_ctx *c)
+{
+    const mmk::Geo &g = c->g;
+    const size_t N = (size_t)g.N;
+    Carve cv;
+    c->o_K = cv.take(sizeof(float) * 6 * (size_t)g.Hx * g.Hy * g.Hz);
+    c->o_ms = cv.take(sizeof(float) * N);
+    c->o_h = cv.take(sizeof(float) * 3 * N);
+    c->o_part = cv.take(sizeof(double) * 8 * mmk::kEnergyBlocks + sizeof(double) * 8);
+    c->o_flag = cv.take(256);
+    // region shared by the step buffers and the tensor-build temporaries
+    const size_t region = cv.off;
+    Carve st;
+    st.off = region;
+    c->o_S1 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.ny);
+    c->o_S2 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.Py);
+    c->o_mtmp = st.take(sizeof(float) * 3 * N);
+    Carve tb;
+    tb.off = region;
+    c->o_T = tb.take(sizeof(double) * 6 * N);
+    size_t a1 = (size_t)g.nz * g.ny * g.Hx, a2 = (size_t)g.Hz * g.Hy * g.Hx;
+    c->o_tA = tb.take(sizeof(double) * (a1 > a2 ? a1 : a2));
+    c->o_tB = tb.take(sizeof(double) * (size_t)g.nz * g.Hy * g.Hx);
+    c->total = st.off > tb.off ? st.off : tb.off;
+}
+
+mm_status need_ws(mm_ctx *c)
+{
+    if (!c->ws) return fail(c, MM_ESTATE, "no workspace set (mm_set_workspace)");
+    return MM_OK;
+}
+
+mm_status set_device(mm_ctx *c) { return hipcheck(c, hipSetDevice(c->device), "hipSetDevice"); }
+
+mmk::LocalParams local_params(const mm_ctx *c)
+{
+    mmk::LocalParams p{};
+    const mm_material &m = c->mat;
+    p.ms = (float)m.Ms;
+    p.ax = (float)(2.0 * m.A / (kMu0 * c->d[0] * c->d[0]));
+    p.ay = (float)(2.0 * m.A / (kMu0 * c->d[1] * c->d[1]));
+    p.az = (float)(2.0 * m.A / (kMu0 * c->d[2] * c->d[2]));
+    p.ku2 = (float)(2.0 * m.Ku / kMu0);
+    p.u0 = (float)m.u[0];
+    p.u1 = (float)m.u[1];
+    p.u2 = (float)m.u[2];
+    p.h0 = (float)c->hext[0];
+    p.h1 = (float)c->hext[1];
+    p.h2 = (float)c->hext[2];
+    const double c1 = -m.gamma0 / (1.0 + m.alpha * m.alpha);
+    p.c1 = (float)c1;
+    p.c2 = (float)(m.alpha * c1);
+    return p;
+}
+
+const float *ms_map_ptr(const mm_ctx *c) { return c->ms_map ? c->at<float>(c->o_ms) : nullptr; }
+const float *h_map_ptr(const mm_ctx *c) { return c->h_map ? c->at<float>(c->o_h) : nullptr; }
+
+// H_demag of m into the S2 region (aliased, 3N floats); returns the pointer
+mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd)
+{
+    const mmk::Geo &g = c->g;
+    float2 *S1 = c->at<float2>(c->o_S1), *S2 = c->at<float2>(c->o_S2);
+    float *H = c->at<float>(c->o_S2);
+    MM_TRY(hipcheck(c, mmk::launch_xfwd(g, m, ms_map_ptr(c), (float)c->mat.Ms, S1, c->stream), "xfwd"));
+    MM_TRY(hipcheck(c, mmk::launch_yfwd(g, S1, S2, c->stream), "yfwd"));
+    MM_TRY(hipcheck(c, mmk::launch_zconv(g, S2, c->at<float>(c->o_K), comp, c->stream), "zconv"));
+    MM_TRY(hipcheck(c, mmk::launch_yinv(g, S2, S1, c->stream), "yinv"));
+    MM_TRY(hipcheck(c, mmk::launch_xinv(g, S1, H, c->stream), "xinv"));
+    *Hd = H;
+    return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_create(mm_ctx **out, const mm_geometry *geo, int device, void *hip_stream)
+{
+    if (!out || !geo) return MM_EINVAL;
+    *out = nullptr;
+    if (geo->nx < 2 || geo->nx > kMaxN || geo->ny < 1 || geo->ny > kMaxN || geo->nz < 1 || geo->nz > kMaxN)
+        return MM_EINVAL;
+    if (!(geo->dx > 0) || !(geo->dy > 0) || !(geo->dz > 0) || !std::isfinite(geo->dx) ||
+        !std::isfinite(geo->dy) || !std::isfinite(geo->dz))
+        return MM_EINVAL;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MM_EINVAL;
+    mm_ctx *c = new (std::nothrow) mm_ctx();
+    if (!c) return MM_ENOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    mmk::Geo &g = c->g;
+    g.nx = geo->nx;
+    g.ny = geo->ny;
+    g.nz = geo->nz;
+    g.Px = padded(g.nx);
+    g.Py = padded(g.ny);
+    g.Pz = padded(g.nz);
+    g.Hx = g.Px / 2 + 1;
+    g.Hy = g.Py == 1 ? 1 : g.Py / 2 + 1;
+    g.Hz = g.Pz == 1 ? 1 : g.Pz / 2 + 1;
+    g.N = (long long)g.nx * g.ny * g.nz;
+    c->d[0] = geo->dx;
+    c->d[1] = geo->dy;
+    c->d[2] = geo->dz;
+    layout(c);
+    mm_status s = set_device(c);
+    if (s == MM_OK) s = init_device(c);
+    if (s != MM_OK) {
+        delete c;
+        return s;
+    }
+    *out = c;
+    return MM_OK;
+}
+
+mm_status mm_destroy(mm_ctx *c)
+{
+    if (!c) return MM_EINVAL;
+    delete c;
+    return MM_OK;
+}
+
+mm_status mm_set_stream(mm_ctx *c, void *hip_stream)
+{
+    if (!c) return MM_EINVAL;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    return MM_OK;
+}
+
+mm_status mm_workspace_size(const mm_ctx *c, size_t *bytes)
+{
+    if (!c || !bytes) return MM_EINVAL;
+    *bytes = c->total;
+    return MM_OK;
+}
+
+mm_status mm_set_workspace(mm_ctx *c, void *dev_ptr, size_t bytes)
+{
+    if (!c) return MM_EINVAL;
+    if (!dev_ptr) return fail(c, MM_EINVAL, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) return fail(c, MM_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < c->total)
+        return fail(c, MM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, c->total);
+    c->ws = static_cast<char *>(dev_ptr);
+    c->ws_bytes = bytes;
+    c->tensor = false;
+    c->ms_map = false;
+    c->h_map = false;
+    MM_TRY(set_device(c));
+    return hipcheck(c, hipMemsetAsync(c->at<int>(c->o_flag), 0, sizeof(int), c->stream), "clear flag");
+}
+
+mm_status mm_set_material(mm_ctx *c, const mm_material *m)
+{
+    if (!c) return MM_EINVAL;
+    if (!m) return fail(c, MM_EINVAL, "material is NULL");
+    const double un = std::sqrt(m->u[0] * m->u[0] + m->u[1] * m->u[1] + m->u[2] * m->u[2]);
+    if (!(m->Ms > 0) || !std::isfinite(m->Ms)) return fail(c, MM_EINVAL, "Ms must be > 0");
+    if (!(m->A >= 0) || !std::isfinite(m->A)) return fail(c, MM_EINVAL, "A must be >= 0");
+    if (!(m->Ku >= 0) || !std::isfinite(m->Ku)) return fail(c, MM_EINVAL, "Ku must be >= 0");
+    if (!(un > 0) || !std::isfinite(un)) return fail(c, MM_EINVAL, "anisotropy axis must be non-zero");
+    if (!(m->alpha >= 0) || !std::isfinite(m->alpha)) return fail(c, MM_EINVAL, "alpha must be >= 0");
+    if (!(m->gamma0 > 0) || !std::isfinite(m->gamma0)) return fail(c, MM_EINVAL, "gamma0 must be > 0");
+    c->mat = *m;
+    for (int i = 0; i < 3; ++i) c->mat.u[i] = m->u[i] / un;
+    c->have_mat = true;
+    return MM_OK;
+}
+
+mm_status mm_set_ms_map(mm_ctx *c, const float *ms)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(need_ws(c));
+    if (!ms) {
+        c->ms_map = false;
+        return MM_OK;
+    }
+    if (!aligned16(ms)) return fail(c, MM_EINVAL, "Ms map must be 16-byte aligned");
+    MM_TRY(set_device(c));
+    MM_TRY(hipcheck(c, hipMemcpyAsync(c->at<float>(c->o_ms), ms, sizeof(float) * c->g.N, hipMemcpyDeviceToDevice,
+                                      c->stream), "copy Ms map"));
+    c->ms_map = true;
+    return MM_OK;
+}
+
+mm_status mm_set_hext(mm_ctx *c, const double h[3])
+{
+    if (!c) return MM_EINVAL;
+    if (!h) return fail(c, MM_EINVAL, "field is NULL");
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(h[i])) return fail(c, MM_EINVAL, "field must be finite");
+    for (int i = 0; i < 3; ++i) c->hext[i] = h[i];
+    return MM_OK;
+}
+
+mm_status mm_set_hext_map(mm_ctx *c, const float *h)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(need_ws(c));
+    if (!h) {
+        c->h_map = false;
+        return MM_OK;
+    }
+    if (!aligned16(h)) return fail(c, MM_EINVAL, "field map must be 16-byte aligned");
+    MM_TRY(set_device(c));
+    MM_TRY(hipcheck(c, hipMemcpyAsync(c->at<float>(c->o_h), h, sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice,
+                                      c->stream), "copy field map"));
+    c->h_map = true;
+    return MM_OK;
+}
+
+mm_status mm_tensor_table(mm_ctx *c, double *tab)
+{
+    if (!c) return MM_EINVAL;
+    if (!tab || !aligned16(tab)) return fail(c, MM_EINVAL, "table pointer must be non-NULL and 16-byte aligned");
+    MM_TRY(set_device(c));
+    MM_TRY(hipcheck(c, mmk::launch_tensor_octant(c->g, c->d[0], c->d[1], c->d[2], tab, c->stream), "tensor octant"));
+    return hipcheck(c, hipStreamSynchronize(c->stream), "tensor table sync");
+}
+
+mm_status mm_build_tensor(mm_ctx *c)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(need_ws(c));
+    MM_TRY(set_device(c));
+    double *T = c->at<double>(c->o_T);
+    MM_TRY(hipcheck(c, mmk::launch_tensor_octant(c->g, c->d[0], c->d[1], c->d[2], T, c->stream), "tensor octant"));
+    MM_TRY(hipcheck(c, mmk::launch_tensor_spectrum(c->g, T, c->at<double>(c->o_tA), c->at<double>(c->o_tB),
+                                                   c->at<float>(c->o_K), c->stream),
+                    "tensor spectrum"));
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "tensor build sync"));
+    c->tensor = true;
+    return MM_OK;
+}
+
+mm_status mm_compute_heff(mm_ctx *c, const float *m, float *h, uint32_t terms)
+{
+    if (!c) return MM_EINVAL;
+    if (!m || !h || !aligned16(m) || !aligned16(h)) return fail(c, MM_EINVAL, "m and h must be 16-byte aligned device pointers");
+    if (m == h) return fail(c, MM_EINVAL, "h may not alias m");
+    if (terms & ~uint32_t(MM_T_ALL)) return fail(c, MM_EINVAL, "unknown term bits 0x%x", terms);
+    MM_TRY(need_ws(c));
+    if (!c->have_mat) return fail(c, MM_ESTATE, "material not set");
+    if ((terms & MM_T_DEMAG) && !c->tensor) return fail(c, MM_ESTATE, "demag requested before mm_build_tensor");
+    MM_TRY(set_device(c));
+    float *Hd = nullptr;
+    if (terms & MM_T_DEMAG) MM_TRY(demag(c, m, false, &Hd));
+    return hipcheck(c, mmk::launch_local(c->g, local_params(c), m, Hd, ms_map_ptr(c), h_map_ptr(c), terms, 0, 0.f, 0,
+                                         nullptr, h, c->at<int>(c->o_flag), c->stream),
+                    "local field");
+}
+
+mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
+{
+    if (!c) return MM_EINVAL;
+    if (!m || !aligned16(m)) return fail(c, MM_EINVAL, "m must be a 16-byte aligned device pointer");
+    if (nsteps < 0) return fail(c, MM_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MM_EINVAL, "dt must be finite and > 0");
+    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED)) return fail(c, MM_EINVAL, "unknown flag bits 0x%x", flags);
+    MM_TRY(need_ws(c));
+    if (!c->have_mat) return fail(c, MM_ESTATE, "material not set");
+    if (!c->tensor) return fail(c, MM_ESTATE, "mm_build_tensor has not been called");
+    MM_TRY(set_device(c));
+    const mmk::LocalParams p = local_params(c);
+    const bool comp = flags & MM_F_COMPENSATED;
+    const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
+    float *buf[2] = {m, c->at<float>(c->o_mtmp)};
+    int *flag = c->at<int>(c->o_flag);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const float *src = buf[s & 1];
+        float *dst = buf[(s + 1) & 1];
+        float *Hd = nullptr;
+        MM_TRY(demag(c, src, comp, &Hd));
+        MM_TRY(hipcheck(c, mmk::launch_local(c->g, p, src, Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt,
+                                             renorm, dst, nullptr, flag, c->stream),
+                        "llg step"));
+    }
+    if (nsteps & 1)
+        MM_TRY(hipcheck(c, hipMemcpyAsync(m, buf[1], sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice, c->stream),
+                        "copy back state"));
+    return MM_OK;
+}
+
+mm_status mm_reduce(mm_ctx *c, const float *m, double *out)
+{
+    if (!c) return MM_EINVAL;
+    if (!m || !out || !aligned16(m) || !aligned16(out)) return fail(c, MM_EINVAL, "m and out must be 16-byte aligned device pointers");
+    MM_TRY(need_ws(c));
+    if (!c->have_mat) return fail(c, MM_ESTATE, "material not set");
+    if (!c->tensor) return fail(c, MM_ESTATE, "mm_build_tensor has not been called");
+    MM_TRY(set_device(c));
+    float *Hd = nullptr;
+    MM_TRY(demag(c, m, false, &Hd));
+    mmk::EnergyParams e{};
+    e.A = c->mat.A;
+    e.Ku = c->mat.Ku;
+    e.u0 = c->mat.u[0];
+    e.u1 = c->mat.u[1];
+    e.u2 = c->mat.u[2];
+    e.ms = c->mat.Ms;
+    e.h0 = c->hext[0];
+    e.h1 = c->hext[1];
+    e.h2 = c->hext[2];
+    e.cx = 1.0 / (c->d[0] * c->d[0]);
+    e.cy = 1.0 / (c->d[1] * c->d[1]);
+    e.cz = 1.0 / (c->d[2] * c->d[2]);
+    e.V = c->d[0] * c->d[1] * c->d[2];
+    e.mu0 = kMu0;
+    e.terms = MM_T_ALL;
+    return hipcheck(c, mmk::launch_energy(c->g, e, m, Hd, ms_map_ptr(c), h_map_ptr(c), c->at<double>(c->o_part), out,
+                                          c->stream),
+                    "energy");
+}
+
+mm_status mm_sync(mm_ctx *c)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(set_device(c));
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "stream sync"));
+    if (c->ws) {
+        int flag = 0;
+        MM_TRY(hipcheck(c, hipMemcpy(&flag, c->at<int>(c->o_flag), sizeof(int), hipMemcpyDeviceToHost), "read flag"));
+        if (flag) {
+            MM_TRY(hipcheck(c, hipMemset(c->at<int>(c->o_flag), 0, sizeof(int)), "clear flag"));
+            return fail(c, MM_ENONFINITE, "a step produced a non-finite magnetisation");
+        }
+    }
+    return MM_OK;
+}
+
+const char *mm_last_error(const mm_ctx *c)
+{
+    if (!c) return "null context";
+    return c->err.c_str();
+}
+
+}  // extern "C"

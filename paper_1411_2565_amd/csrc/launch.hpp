@@ -1,0 +1,62 @@
+// launch.hpp -- host-side launchers of the gfx950 kernels (kernels.hip).
+// Every launcher enqueues on `s` and returns the hipError_t of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmk {
+
+// Grid sizes and padded FFT sizes of one sample.
+struct Geo {
+    int nx, ny, nz;   // cells
+    int Px, Py, Pz;   // padded lengths (powers of two, or 1 for a single-cell axis)
+    int Hx, Hy, Hz;   // stored spectral lengths P/2 + 1 (1 when P = 1)
+    long long N;      // nx*ny*nz
+};
+
+// Coefficients of the local field terms and of the LLG update, FP32.
+struct LocalParams {
+    float ms;            // uniform Ms (A/m), used when no map is given
+    float ax, ay, az;    // 2A/(mu0 d^2) per axis: exchange field = (a/Ms) * sum (m_nb - m)
+    float ku2;           // 2Ku/mu0: anisotropy field = (ku2/Ms) (m.u) u
+    float u0, u1, u2;    // easy axis
+    float h0, h1, h2;    // uniform external field (A/m)
+    float c1, c2;        // LLG: f = c1 m x H + c2 m x (m x H)
+};
+
+// FP64 energy coefficients.
+struct EnergyParams {
+    double A, Ku, u0, u1, u2, ms, h0, h1, h2;
+    double cx, cy, cz;  // 1/d^2
+    double V;           // cell volume
+    double mu0;
+    uint32_t terms;
+};
+
+constexpr int kEnergyBlocks = 512;
+
+hipError_t init_tables(hipStream_t s);
+
+// demag pipeline
+hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s);
+hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s);
+hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool compensated, hipStream_t s);
+hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s);
+hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s);
+
+// local terms: mode 0 writes H to out_h, mode 1 writes the Euler step to out_m
+hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
+                        const float *ms_map, const float *h_map, uint32_t terms, int mode,
+                        float dt, int renorm, float *out_m, float *out_h, int *flag, hipStream_t s);
+
+// FP64 reductions
+hipError_t launch_energy(const Geo &g, const EnergyParams &p, const float *m, const float *Hd,
+                         const float *ms_map, const float *h_map, double *partials, double *out,
+                         hipStream_t s);
+
+// FP64 tensor build
+hipError_t launch_tensor_octant(const Geo &g, double dx, double dy, double dz, double *T, hipStream_t s);
+hipError_t launch_tensor_spectrum(const Geo &g, const double *T, double *tmpA, double *tmpB, float *K,
+                                  hipStream_t s);
+
+}  // namespace mmk
