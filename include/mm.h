@@ -153,6 +153,29 @@ mm_status mm_step_llg(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32
  *     E_zeeman = -mu0 V sum Ms m . h_ext */
 mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
 
+/* Kernel identifiers for mm_kernel_times. */
+enum {
+    MM_K_XFWD = 0,   /* x-forward real FFT (transposed write) */
+    MM_K_YFWD = 1,   /* y-forward FFT */
+    MM_K_ZCONV = 2,  /* z FFT + tensor multiply + inverse z FFT */
+    MM_K_YINV = 3,   /* y-inverse FFT */
+    MM_K_XINV = 4,   /* x-inverse real FFT -> H_demag */
+    MM_K_LOCAL = 5,  /* local field terms + Euler LLG update */
+    MM_K_COUNT = 6
+};
+
+/* Diagnostic timing: while enabled, every kernel launched by mm_step_llg and
+ * mm_compute_heff is bracketed by two HIP events on the context's stream and
+ * its duration is accumulated per kernel identifier.  Enabling clears the
+ * totals.  Events serialise nothing that the single stream does not already
+ * serialise. */
+mm_status mm_kernel_timing(mm_ctx *c, int enable);
+
+/* Synchronise the stream, fold pending event pairs into the totals and
+ * return, per MM_K_* identifier, the accumulated milliseconds (ms[MM_K_COUNT])
+ * and number of launches (launches[MM_K_COUNT]); host pointers. */
+mm_status mm_kernel_times(mm_ctx *c, double *ms, int64_t *launches);
+
 /* Wait for the context's stream; report a HIP error or a non-finite state
  * flagged by an earlier step (MM_ENONFINITE, flag cleared on report). */
 mm_status mm_sync(mm_ctx *c);

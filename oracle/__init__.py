@@ -65,6 +65,8 @@ def lib():
         L.orc_energy.argtypes = [P, _D, _D]
         L.orc_adjoint.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, _D, _D, _D, _D]
         L.orc_adjoint.restype = ctypes.c_double
+        L.orc_step_cells.argtypes = [P, _D, _I64, ctypes.c_int64, ctypes.c_double, _D]
+        L.orc_threads.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -185,6 +187,17 @@ class Problem:
                       _p(tr) if traj else ctypes.cast(None, _D))
         return (m, tr) if traj else m
 
+    def step_cells(self, m, cells, dt):
+        """One Euler step evaluated only at the given linear cell indices
+        (all sources enter the demag sum): updated m there, [3][ncells]."""
+        m = _f64(m, self._shape())
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((3, cells.size))
+        st = self._struct()
+        lib().orc_step_cells(ctypes.byref(st), _p(m), cells.ctypes.data_as(_I64), cells.size,
+                             float(dt), _p(out))
+        return out
+
     def energy(self, m):
         m = _f64(m, self._shape())
         out = np.zeros(5)
@@ -204,6 +217,11 @@ class Problem:
         loss = lib().orc_adjoint(ctypes.byref(st), _p(m0), int(nsteps), float(dt), _p(t),
                                  _p(gm), _p(gh), _p(gms))
         return loss, gm, gh, gms
+
+
+def threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return lib().orc_threads()
 
 
 def conv(n, tab, v):

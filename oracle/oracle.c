@@ -35,6 +35,7 @@
  * stored [6][nz][ny][nx] in the component order xx, yy, zz, xy, xz, yz.
  */
 #include <math.h>
+#include <omp.h>
 #include <stddef.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -359,6 +360,68 @@ void orc_demag_observers(const orc_problem *p, const double *m,
 }
 
 /* ------------------------------------------------------------------------ */
+/* One Euler step evaluated at a list of cells only (every source still      */
+/* enters the demag sum): out[3][nobs] is the updated m at those cells.      */
+/* Used to time the oracle on a bounded sample of a large workload.          */
+/* ------------------------------------------------------------------------ */
+static void cross3(const double a[3], const double b[3], double c[3]);
+
+void orc_step_cells(const orc_problem *p, const double *m, const int64_t *obs, int64_t nobs,
+                    double dt, double *out)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const size_t N = (size_t)nx * ny * nz;
+    double *Hd = (double *)calloc(3 * (size_t)nobs, sizeof(double));
+    if (p->terms & ORC_T_DEMAG) orc_demag_observers(p, m, obs, nobs, Hd);
+    const double c1 = -p->gamma0 / (1.0 + p->alpha * p->alpha), c2 = p->alpha * c1;
+    const double cd[3] = {1.0 / (p->dx * p->dx), 1.0 / (p->dy * p->dy), 1.0 / (p->dz * p->dz)};
+    for (int64_t q = 0; q < nobs; ++q) {
+        const int64_t i = obs[q];
+        const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((int64_t)nx * ny));
+        const double mi[3] = {m[i], m[N + i], m[2 * N + i]};
+        double h[3] = {Hd[q], Hd[nobs + q], Hd[2 * nobs + q]};
+        if (p->terms & ORC_T_EXCH) {
+            const int coord[3] = {ix, iy, iz}, n[3] = {nx, ny, nz};
+            const int64_t stride[3] = {1, nx, (int64_t)nx * ny};
+            const double k = 2.0 * p->A / (ORC_MU0 * p->Ms[i]);
+            for (int a = 0; a < 3; ++a)
+                for (int s = -1; s <= 1; s += 2) {
+                    const int cc = coord[a] + s;
+                    if (cc < 0 || cc >= n[a]) continue;
+                    const int64_t j = i + s * stride[a];
+                    for (int c = 0; c < 3; ++c) h[c] += k * cd[a] * (m[c * N + j] - mi[c]);
+                }
+        }
+        if (p->terms & ORC_T_ANIS) {
+            const double mu = mi[0] * p->u[0] + mi[1] * p->u[1] + mi[2] * p->u[2];
+            for (int c = 0; c < 3; ++c) h[c] += 2.0 * p->Ku / (ORC_MU0 * p->Ms[i]) * mu * p->u[c];
+        }
+        if (p->terms & ORC_T_ZEEMAN)
+            for (int c = 0; c < 3; ++c) h[c] += p->hext[c * N + i];
+        double mxh[3], mxmxh[3], v[3];
+        cross3(mi, h, mxh);
+        cross3(mi, mxh, mxmxh);
+        for (int c = 0; c < 3; ++c) v[c] = mi[c] + dt * (c1 * mxh[c] + c2 * mxmxh[c]);
+        double nrm = 1.0;
+        if (p->renorm) nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        for (int c = 0; c < 3; ++c) out[c * nobs + q] = v[c] / nrm;
+    }
+    free(Hd);
+}
+
+/* number of OpenMP threads the oracle runs with */
+int orc_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Local field terms.                                                        */
 /* ------------------------------------------------------------------------ */
 
@@ -424,6 +487,8 @@ static inline void cross(const double a[3], const double b[3], double c[3])
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
+
+static void cross3(const double a[3], const double b[3], double c[3]) { cross(a, b, c); }
 
 void orc_llg_rhs(const orc_problem *p, const double *m, const double *H, double *f)
 {

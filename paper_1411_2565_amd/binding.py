@@ -67,6 +67,8 @@ def load():
         "mm_step_llg": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32],
         "mm_reduce": [_P, _P, _P],
         "mm_sync": [_P],
+        "mm_kernel_timing": [_P, ctypes.c_int],
+        "mm_kernel_times": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -183,6 +185,22 @@ def mm_reduce(ctx, m, out, N):
 
 def mm_sync(ctx):
     _check(ctx, load().mm_sync(ctx), "mm_sync")
+
+
+MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local"]
+
+
+def mm_kernel_timing(ctx, enable):
+    _check(ctx, load().mm_kernel_timing(ctx, int(bool(enable))), "mm_kernel_timing")
+
+
+def mm_kernel_times(ctx):
+    """{kernel name: (total ms, launches)} accumulated since timing was enabled."""
+    n = len(MM_K_NAMES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(ctx, load().mm_kernel_times(ctx, ms, cnt), "mm_kernel_times")
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(MM_K_NAMES)}
 
 
 # -------------------------------------------------------------- convenience

@@ -17,6 +17,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "launch.hpp"
 
@@ -52,6 +53,22 @@ struct mm_ctx {
     size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_T = 0, o_tA = 0, o_tB = 0;
     size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, total = 0;
     std::string err;
+    // diagnostic per-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_free;
+    struct Pending { int kernel; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    double t_ms[MM_K_COUNT] = {0};
+    int64_t t_n[MM_K_COUNT] = {0};
+
+    ~mm_ctx()
+    {
+        for (auto &p : pending) {
+            hipEventDestroy(p.a);
+            hipEventDestroy(p.b);
+        }
+        for (auto e : ev_free) hipEventDestroy(e);
+    }
 
     template <typename T>
     T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
@@ -135,6 +152,50 @@ void layout(mm_ctx *c)
     c->total = st.off > tb.off ? st.off : tb.off;
 }
 
+// fold completed event pairs into the per-kernel totals (stream synchronised)
+mm_status drain_timing(mm_ctx *c)
+{
+    if (c->pending.empty()) return MM_OK;
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "timing sync"));
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        MM_TRY(hipcheck(c, hipEventElapsedTime(&ms, p.a, p.b), "event elapsed"));
+        c->t_ms[p.kernel] += ms;
+        c->t_n[p.kernel] += 1;
+        c->ev_free.push_back(p.a);
+        c->ev_free.push_back(p.b);
+    }
+    c->pending.clear();
+    return MM_OK;
+}
+
+hipEvent_t take_event(mm_ctx *c)
+{
+    if (c->ev_free.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        return e;
+    }
+    hipEvent_t e = c->ev_free.back();
+    c->ev_free.pop_back();
+    return e;
+}
+
+// run one launcher, bracketed by events when timing is on
+template <typename F>
+mm_status timed(mm_ctx *c, int kernel, const char *what, F &&launch)
+{
+    if (!c->timing) return hipcheck(c, launch(), what);
+    if (c->pending.size() >= 2048) MM_TRY(drain_timing(c));
+    hipEvent_t a = take_event(c), b = take_event(c);
+    if (!a || !b) return fail(c, MM_EHIP, "hipEventCreate failed");
+    MM_TRY(hipcheck(c, hipEventRecord(a, c->stream), "event record"));
+    MM_TRY(hipcheck(c, launch(), what));
+    MM_TRY(hipcheck(c, hipEventRecord(b, c->stream), "event record"));
+    c->pending.push_back({kernel, a, b});
+    return MM_OK;
+}
+
 mm_status need_ws(mm_ctx *c)
 {
     if (!c->ws) return fail(c, MM_ESTATE, "no workspace set (mm_set_workspace)");
@@ -173,11 +234,13 @@ mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd)
     const mmk::Geo &g = c->g;
     float2 *S1 = c->at<float2>(c->o_S1), *S2 = c->at<float2>(c->o_S2);
     float *H = c->at<float>(c->o_S2);
-    MM_TRY(hipcheck(c, mmk::launch_xfwd(g, m, ms_map_ptr(c), (float)c->mat.Ms, S1, c->stream), "xfwd"));
-    MM_TRY(hipcheck(c, mmk::launch_yfwd(g, S1, S2, c->stream), "yfwd"));
-    MM_TRY(hipcheck(c, mmk::launch_zconv(g, S2, c->at<float>(c->o_K), comp, c->stream), "zconv"));
-    MM_TRY(hipcheck(c, mmk::launch_yinv(g, S2, S1, c->stream), "yinv"));
-    MM_TRY(hipcheck(c, mmk::launch_xinv(g, S1, H, c->stream), "xinv"));
+    const float *K = c->at<float>(c->o_K);
+    hipStream_t s = c->stream;
+    MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, ms_map_ptr(c), (float)c->mat.Ms, S1, s); }));
+    MM_TRY(timed(c, MM_K_YFWD, "yfwd", [&] { return mmk::launch_yfwd(g, S1, S2, s); }));
+    MM_TRY(timed(c, MM_K_ZCONV, "zconv", [&] { return mmk::launch_zconv(g, S2, K, comp, s); }));
+    MM_TRY(timed(c, MM_K_YINV, "yinv", [&] { return mmk::launch_yinv(g, S2, S1, s); }));
+    MM_TRY(timed(c, MM_K_XINV, "xinv", [&] { return mmk::launch_xinv(g, S1, H, s); }));
     *Hd = H;
     return MM_OK;
 }
@@ -358,9 +421,11 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m, float *h, uint32_t terms)
     MM_TRY(set_device(c));
     float *Hd = nullptr;
     if (terms & MM_T_DEMAG) MM_TRY(demag(c, m, false, &Hd));
-    return hipcheck(c, mmk::launch_local(c->g, local_params(c), m, Hd, ms_map_ptr(c), h_map_ptr(c), terms, 0, 0.f, 0,
-                                         nullptr, h, c->at<int>(c->o_flag), c->stream),
-                    "local field");
+    const mmk::LocalParams p = local_params(c);
+    return timed(c, MM_K_LOCAL, "local field", [&] {
+        return mmk::launch_local(c->g, p, m, Hd, ms_map_ptr(c), h_map_ptr(c), terms, 0, 0.f, 0, nullptr, h,
+                                 c->at<int>(c->o_flag), c->stream);
+    });
 }
 
 mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
@@ -384,9 +449,10 @@ mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t f
         float *dst = buf[(s + 1) & 1];
         float *Hd = nullptr;
         MM_TRY(demag(c, src, comp, &Hd));
-        MM_TRY(hipcheck(c, mmk::launch_local(c->g, p, src, Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt,
-                                             renorm, dst, nullptr, flag, c->stream),
-                        "llg step"));
+        MM_TRY(timed(c, MM_K_LOCAL, "llg step", [&] {
+            return mmk::launch_local(c->g, p, src, Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt, renorm,
+                                     dst, nullptr, flag, c->stream);
+        }));
     }
     if (nsteps & 1)
         MM_TRY(hipcheck(c, hipMemcpyAsync(m, buf[1], sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice, c->stream),
@@ -423,6 +489,33 @@ mm_status mm_reduce(mm_ctx *c, const float *m, double *out)
     return hipcheck(c, mmk::launch_energy(c->g, e, m, Hd, ms_map_ptr(c), h_map_ptr(c), c->at<double>(c->o_part), out,
                                           c->stream),
                     "energy");
+}
+
+mm_status mm_kernel_timing(mm_ctx *c, int enable)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(set_device(c));
+    MM_TRY(drain_timing(c));
+    c->timing = enable != 0;
+    if (c->timing)
+        for (int k = 0; k < MM_K_COUNT; ++k) {
+            c->t_ms[k] = 0.0;
+            c->t_n[k] = 0;
+        }
+    return MM_OK;
+}
+
+mm_status mm_kernel_times(mm_ctx *c, double *ms, int64_t *launches)
+{
+    if (!c) return MM_EINVAL;
+    if (!ms || !launches) return fail(c, MM_EINVAL, "output pointers are NULL");
+    MM_TRY(set_device(c));
+    MM_TRY(drain_timing(c));
+    for (int k = 0; k < MM_K_COUNT; ++k) {
+        ms[k] = c->t_ms[k];
+        launches[k] = c->t_n[k];
+    }
+    return MM_OK;
 }
 
 mm_status mm_sync(mm_ctx *c)

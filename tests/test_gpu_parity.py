@@ -106,7 +106,7 @@ def _block16(**kw):
 
 @pytest.mark.parametrize("terms", [1, 2, 4, 8, 15])
 def test_heff_terms_block16(gpu_lib, terms):
-    w, m0, args = _block16(Ku=3e4, u=(0.3, 0.4, 0.866), hext=(1e4, -2e4, 5e3))
+    w, m0, args = _block16(Ku=3e4, u=(0.48, 0.6, 0.64), hext=(1e4, -2e4, 5e3))
     sim = gpu_lib.Sim(w.n, w.d, **args)
     mf = host(gpu(m0))
     H = host(sim.heff(gpu(m0), terms))

@@ -165,6 +165,18 @@ def test_observer_subset_matches_full():
     np.testing.assert_allclose(P.demag_observers(m, obs), H[:, obs], rtol=1e-13, atol=1e-9)
 
 
+def test_step_cells_equals_full_step_at_those_cells():
+    n, d = (9, 6, 3), (4e-9, 4e-9, 3e-9)
+    rng = np.random.default_rng(21)
+    m = rng.standard_normal((3, 3, 6, 9))
+    m /= np.linalg.norm(m, axis=0)
+    P = oracle.Problem(n, d, Ms=8e5 * (0.6 + rng.random((3, 6, 9))), Ku=2e4, u=(0, 0.6, 0.8),
+                       hext=rng.standard_normal((3, 3, 6, 9)) * 1e4, alpha=0.2)
+    cells = np.array([0, 8, 9, 53, 100, 161])
+    full = P.run(m, 1, 3e-14).reshape(3, -1)[:, cells]
+    np.testing.assert_allclose(P.step_cells(m, cells, 3e-14), full, rtol=1e-12, atol=1e-14)
+
+
 def test_convolution_is_self_adjoint():
     n, d = (6, 5, 3), (4e-9, 4e-9, 3e-9)
     tab = oracle.tensor_table(n, d)
