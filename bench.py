@@ -78,6 +78,43 @@ def cpu_baseline(w, m0, target_s=12.0):
                        f"{t_tab:.1f} s not counted")}
 
 
+def adjoint_ratio(binding, T=2000):
+    """Backward (segment replay + hand-written adjoint) over forward wall time
+    of a T-step rollout on the 128x128x4 film, per-cell field and Ms maps,
+    L2 loss to the target pattern, sqrt(T) checkpoints."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    from paper_1411_2565_amd.rollout import rollout
+    w = workloads.FILM_128x128x4
+    m0, ms, h, t = workloads.adjoint_inputs(w)
+    dev = torch.device("cuda", 0)
+    f32 = dict(dtype=torch.float32, device=dev)
+    sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, device=0)
+    tgt = torch.tensor(t, **f32)
+
+    def once():
+        m0g = torch.tensor(m0, **f32).requires_grad_(True)
+        hg = torch.tensor(h, **f32).requires_grad_(True)
+        msg = torch.tensor(ms, **f32).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mT = rollout(m0g, hg, msg, sim, T, w.dt)
+        loss = 0.5 * ((mT - tgt) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    once()  # warm-up
+    fwd, bwd = once()
+    sim.close()
+    return {"workload": "film 128x128x4, 5 nm cubes, T=2000, dt=1e-13, maps of h_ext and Ms, "
+                        "checkpoint every 45 steps",
+            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "ratio": round(bwd / fwd, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,6 +124,7 @@ def main():
                     help="steps of the per-kernel event-timed region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--compensated", action="store_true", help="time the compensated spectral multiply")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -141,6 +179,12 @@ def main():
     ach = kernels[dom]["GBps"]
     step_bytes = sum(kb.values())
 
+    sim.close()
+    adj = None
+    if not args.no_adjoint:
+        print("bench: adjoint/forward ratio on the 128x128x4 film", file=sys.stderr, flush=True)
+        adj = adjoint_ratio(binding)
+
     cpu = None
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
@@ -169,9 +213,9 @@ def main():
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": kernels,
         "tensor_build_s": round(t_build, 3),
+        "adjoint": adj,
     }
     print(json.dumps(line), flush=True)
-    sim.close()
 
 
 if __name__ == "__main__":

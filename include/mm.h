@@ -153,6 +153,29 @@ mm_status mm_step_llg(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32
  *     E_zeeman = -mu0 V sum Ms m . h_ext */
 mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
 
+/* Use (on != 0) or stop using the compensated FP32 spectral multiply in every
+ * demag evaluation of this context (mm_compute_heff, mm_reduce, steps and
+ * adjoint steps), in addition to per-call MM_F_COMPENSATED. */
+mm_status mm_set_compensated(mm_ctx *c, int on);
+
+/* Forward rollout that keeps what the adjoint needs: advances m_dev in place
+ * by nsteps Euler steps exactly as mm_step_llg does, and stores the state
+ * entering step s in m_traj[s] and its demagnetising field in hd_traj[s]
+ * (each nsteps * 3N floats, device, [s][3][nz][ny][nx]). */
+mm_status mm_forward_store(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32_t flags,
+                           float *m_traj, float *hd_traj);
+
+/* Adjoint of one Euler step, the exact transpose of the discrete step
+ * (eq. (3) with the field of eq. (2)), for a loss L of the later states.
+ * Inputs: the state m_n entering the step and its demagnetising field hd_n
+ * (from mm_forward_store), lam = dL/dm_{n+1} (3N floats, device).  Output:
+ * lam is overwritten with dL/dm_n.  g_hext (3N floats) and g_ms (N floats),
+ * when non-NULL, are accumulated with this step's contribution to dL/dh_ext
+ * and dL/dMs (per-cell maps; add up over steps).  The demag transpose is the
+ * same FFT convolution, the tensor being symmetric and even. */
+mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float *lam, float *g_hext,
+                          float *g_ms, double dt, uint32_t flags);
+
 /* Kernel identifiers for mm_kernel_times. */
 enum {
     MM_K_XFWD = 0,   /* x-forward real FFT (transposed write) */
@@ -160,7 +183,7 @@ enum {
     MM_K_ZCONV = 2,  /* z FFT + tensor multiply + inverse z FFT */
     MM_K_YINV = 3,   /* y-inverse FFT */
     MM_K_XINV = 4,   /* x-inverse real FFT -> H_demag */
-    MM_K_LOCAL = 5,  /* local field terms + Euler LLG update */
+    MM_K_LOCAL = 5,  /* local field terms (+ Euler LLG update in mm_step_llg) */
     MM_K_COUNT = 6
 };
 

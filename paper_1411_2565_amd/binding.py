@@ -68,6 +68,9 @@ def load():
         "mm_reduce": [_P, _P, _P],
         "mm_sync": [_P],
         "mm_kernel_timing": [_P, ctypes.c_int],
+        "mm_set_compensated": [_P, ctypes.c_int],
+        "mm_forward_store": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32, _P, _P],
+        "mm_adjoint_step": [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_uint32],
         "mm_kernel_times": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     }
     for name, args in sig.items():
@@ -185,6 +188,29 @@ def mm_reduce(ctx, m, out, N):
 
 def mm_sync(ctx):
     _check(ctx, load().mm_sync(ctx), "mm_sync")
+
+
+def mm_set_compensated(ctx, on):
+    _check(ctx, load().mm_set_compensated(ctx, int(bool(on))), "mm_set_compensated")
+
+
+def mm_forward_store(ctx, m, nsteps, dt, flags, m_traj, hd_traj, N):
+    import torch
+    n = int(nsteps)
+    _check(ctx, load().mm_forward_store(ctx, _dev(m, torch.float32, 3 * N, "m"), n, float(dt), int(flags),
+                                        _dev(m_traj, torch.float32, 3 * N * n, "m_traj") if n else None,
+                                        _dev(hd_traj, torch.float32, 3 * N * n, "hd_traj") if n else None),
+           "mm_forward_store")
+
+
+def mm_adjoint_step(ctx, m_n, hd_n, lam, g_hext, g_ms, dt, flags, N):
+    import torch
+    gh = None if g_hext is None else _dev(g_hext, torch.float32, 3 * N, "g_hext")
+    gm = None if g_ms is None else _dev(g_ms, torch.float32, N, "g_ms")
+    _check(ctx, load().mm_adjoint_step(ctx, _dev(m_n, torch.float32, 3 * N, "m_n"),
+                                       _dev(hd_n, torch.float32, 3 * N, "hd_n"),
+                                       _dev(lam, torch.float32, 3 * N, "lam"), gh, gm, float(dt), int(flags)),
+           "mm_adjoint_step")
 
 
 MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local"]

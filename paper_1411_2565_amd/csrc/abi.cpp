@@ -51,7 +51,8 @@ struct mm_ctx {
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
     size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_T = 0, o_tA = 0, o_tB = 0;
-    size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, total = 0;
+    size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, o_adj = 0, total = 0;
+    bool compensated = false;  // compensated spectral multiply in every demag evaluation
     std::string err;
     // diagnostic per-kernel timing
     bool timing = false;
@@ -64,10 +65,10 @@ struct mm_ctx {
     ~mm_ctx()
     {
         for (auto &p : pending) {
-            hipEventDestroy(p.a);
-            hipEventDestroy(p.b);
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
         }
-        for (auto e : ev_free) hipEventDestroy(e);
+        for (auto e : ev_free) (void)hipEventDestroy(e);
     }
 
     template <typename T>
@@ -136,6 +137,7 @@ void layout(mm_ctx *c)
     c->o_h = cv.take(sizeof(float) * 3 * N);
     c->o_part = cv.take(sizeof(double) * 8 * mmk::kEnergyBlocks + sizeof(double) * 8);
     c->o_flag = cv.take(256);
+    c->o_adj = cv.take(sizeof(float) * 6 * N);  // adjoint: g_H and the local part of lambda
     // region shared by the step buffers and the tensor-build temporaries
     const size_t region = cv.off;
     Carve st;
@@ -228,20 +230,36 @@ mmk::LocalParams local_params(const mm_ctx *c)
 const float *ms_map_ptr(const mm_ctx *c) { return c->ms_map ? c->at<float>(c->o_ms) : nullptr; }
 const float *h_map_ptr(const mm_ctx *c) { return c->h_map ? c->at<float>(c->o_h) : nullptr; }
 
-// H_demag of m into the S2 region (aliased, 3N floats); returns the pointer
-mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd)
+// H_demag of m (M = Ms m, or M = m when unit_ms) into `out` or, if NULL, the
+// S2 region (aliased, 3N floats); *Hd receives the pointer
+mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd, float *out = nullptr, bool unit_ms = false)
 {
     const mmk::Geo &g = c->g;
     float2 *S1 = c->at<float2>(c->o_S1), *S2 = c->at<float2>(c->o_S2);
-    float *H = c->at<float>(c->o_S2);
+    float *H = out ? out : c->at<float>(c->o_S2);
     const float *K = c->at<float>(c->o_K);
     hipStream_t s = c->stream;
-    MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, ms_map_ptr(c), (float)c->mat.Ms, S1, s); }));
+    const float *msm = unit_ms ? nullptr : ms_map_ptr(c);
+    const float ms = unit_ms ? 1.0f : (float)c->mat.Ms;
+    comp = comp || c->compensated;
+    MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, msm, ms, S1, s); }));
     MM_TRY(timed(c, MM_K_YFWD, "yfwd", [&] { return mmk::launch_yfwd(g, S1, S2, s); }));
     MM_TRY(timed(c, MM_K_ZCONV, "zconv", [&] { return mmk::launch_zconv(g, S2, K, comp, s); }));
     MM_TRY(timed(c, MM_K_YINV, "yinv", [&] { return mmk::launch_yinv(g, S2, S1, s); }));
     MM_TRY(timed(c, MM_K_XINV, "xinv", [&] { return mmk::launch_xinv(g, S1, H, s); }));
     *Hd = H;
+    return MM_OK;
+}
+
+mm_status check_step_args(mm_ctx *c, const float *m, int64_t nsteps, double dt, uint32_t flags)
+{
+    if (!m || !aligned16(m)) return fail(c, MM_EINVAL, "m must be a 16-byte aligned device pointer");
+    if (nsteps < 0) return fail(c, MM_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MM_EINVAL, "dt must be finite and > 0");
+    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED)) return fail(c, MM_EINVAL, "unknown flag bits 0x%x", flags);
+    MM_TRY(need_ws(c));
+    if (!c->have_mat) return fail(c, MM_ESTATE, "material not set");
+    if (!c->tensor) return fail(c, MM_ESTATE, "mm_build_tensor has not been called");
     return MM_OK;
 }
 
@@ -431,13 +449,7 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m, float *h, uint32_t terms)
 mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
 {
     if (!c) return MM_EINVAL;
-    if (!m || !aligned16(m)) return fail(c, MM_EINVAL, "m must be a 16-byte aligned device pointer");
-    if (nsteps < 0) return fail(c, MM_EINVAL, "nsteps must be >= 0");
-    if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MM_EINVAL, "dt must be finite and > 0");
-    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED)) return fail(c, MM_EINVAL, "unknown flag bits 0x%x", flags);
-    MM_TRY(need_ws(c));
-    if (!c->have_mat) return fail(c, MM_ESTATE, "material not set");
-    if (!c->tensor) return fail(c, MM_ESTATE, "mm_build_tensor has not been called");
+    MM_TRY(check_step_args(c, m, nsteps, dt, flags));
     MM_TRY(set_device(c));
     const mmk::LocalParams p = local_params(c);
     const bool comp = flags & MM_F_COMPENSATED;
@@ -458,6 +470,68 @@ mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t f
         MM_TRY(hipcheck(c, hipMemcpyAsync(m, buf[1], sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice, c->stream),
                         "copy back state"));
     return MM_OK;
+}
+
+mm_status mm_set_compensated(mm_ctx *c, int on)
+{
+    if (!c) return MM_EINVAL;
+    c->compensated = on != 0;
+    return MM_OK;
+}
+
+mm_status mm_forward_store(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags, float *m_traj,
+                           float *hd_traj)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(check_step_args(c, m, nsteps, dt, flags));
+    if (nsteps > 0 && (!m_traj || !hd_traj || !aligned16(m_traj) || !aligned16(hd_traj)))
+        return fail(c, MM_EINVAL, "trajectory buffers must be 16-byte aligned device pointers");
+    MM_TRY(set_device(c));
+    const size_t S = 3 * (size_t)c->g.N;
+    const mmk::LocalParams p = local_params(c);
+    const bool comp = flags & MM_F_COMPENSATED;
+    const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
+    int *flag = c->at<int>(c->o_flag);
+    if (nsteps > 0)
+        MM_TRY(hipcheck(c, hipMemcpyAsync(m_traj, m, sizeof(float) * S, hipMemcpyDeviceToDevice, c->stream),
+                        "store state"));
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const float *src = m_traj + (size_t)s * S;
+        float *dst = (s + 1 < nsteps) ? m_traj + (size_t)(s + 1) * S : m;
+        float *Hd = nullptr;
+        MM_TRY(demag(c, src, comp, &Hd, hd_traj + (size_t)s * S));
+        MM_TRY(timed(c, MM_K_LOCAL, "llg step", [&] {
+            return mmk::launch_local(c->g, p, src, Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt, renorm,
+                                     dst, nullptr, flag, c->stream);
+        }));
+    }
+    return MM_OK;
+}
+
+mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float *lam, float *g_hext, float *g_ms,
+                          double dt, uint32_t flags)
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(check_step_args(c, m_n, 1, dt, flags));
+    if (!hd_n || !lam || !aligned16(hd_n) || !aligned16(lam))
+        return fail(c, MM_EINVAL, "hd_n and lam must be 16-byte aligned device pointers");
+    if ((g_hext && !aligned16(g_hext)) || (g_ms && !aligned16(g_ms)))
+        return fail(c, MM_EINVAL, "gradient buffers must be 16-byte aligned");
+    MM_TRY(set_device(c));
+    const size_t S = 3 * (size_t)c->g.N;
+    const mmk::LocalParams p = local_params(c);
+    const bool comp = flags & MM_F_COMPENSATED;
+    const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
+    float *gH = c->at<float>(c->o_adj), *lam_loc = gH + S;
+    MM_TRY(timed(c, MM_K_LOCAL, "adjoint local", [&] {
+        return mmk::launch_adj_a(c->g, p, m_n, hd_n, ms_map_ptr(c), h_map_ptr(c), lam, (float)dt, renorm, gH, lam_loc,
+                                 g_hext, g_ms, c->stream);
+    }));
+    float *D = nullptr;
+    MM_TRY(demag(c, gH, comp, &D, nullptr, true));
+    return timed(c, MM_K_LOCAL, "adjoint completion", [&] {
+        return mmk::launch_adj_b(c->g, p, m_n, gH, D, ms_map_ptr(c), lam_loc, lam, g_ms, c->stream);
+    });
 }
 
 mm_status mm_reduce(mm_ctx *c, const float *m, double *out)

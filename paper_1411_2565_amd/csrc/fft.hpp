@@ -2,13 +2,17 @@
 //
 // The demagnetising field is a zero-padded linear convolution evaluated with
 // the discrete convolution theorem (Zhu, arXiv:1411.2565, Sec. 3).  This file
-// holds the 1D transform every pass uses: a Stockham autosort FFT (no bit
-// reversal pass), radix 8 with a final radix-4/4 or radix-2 stage, on lines
-// held in LDS by a whole workgroup.  Forward uses exp(-2 pi i jk/L); the
-// inverse uses exp(+2 pi i jk/L) and is unnormalised.
+// holds the 1D transform every pass uses: a Stockham autosort FFT whose data
+// stays in registers.  A line of length L is spread over L/E threads, E
+// values each, thread t holding positions t + q*(L/E), q < E.  Every radix
+// stage (radix 8, then 4 or 2 to finish) runs in registers; between stages
+// the line is exchanged once through LDS.  The caller loads global memory
+// straight into the first stage's inputs and stores the last stage's outputs
+// straight to global memory; both are in natural order and coalesced.
 //
+// Forward uses exp(-2 pi i jk/L); the inverse exp(+2 pi i jk/L), unnormalised.
 // Twiddles come from one table of exp(-2 pi i t / MAXL), t < MAXL, rounded
-// once from FP64 (init kernel), so every twiddle is within 0.5 ulp.
+// once from FP64, so every twiddle is within 0.5 ulp.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -97,66 +101,77 @@ struct Dft<8, INV> {
     }
 };
 
-// ---- one Stockham stage ----------------------------------------------------
-// Sub-transforms of length Ns are complete on entry; the stage merges R of
-// them into sub-transforms of length Ns*R.  j indexes the L/R butterflies.
-template <int R, bool INV>
-__device__ __forceinline__ void stockham_stage(const float2 *__restrict__ src,
-                                               float2 *__restrict__ dst, int L, int Ns, int j)
-{
-    const int stride = L / R;
-    float2 v[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = src[j + r * stride];
-    const int k = j & (Ns - 1);
-    if (Ns > 1) {
-#pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = cmul(v[r], twiddle<INV>(r * k, Ns * R));
-    }
-    Dft<R, INV>::run(v);
-    const int base = (j - k) * R + k;
-#pragma unroll
-    for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
-}
+// LDS index with one pad slot every 8 complex values (spreads the strided
+// Stockham writes over the banks)
+__device__ __forceinline__ int lpad(int i) { return i + (i >> 3); }
+__host__ __device__ constexpr int lds_line(int L) { return L + L / 8 + 1; }
 
-// radix for the next stage when `rem` = L/Ns points remain to be merged:
-// 8 while possible, ending in 8*4*4 / 8*4 / 4*4 / 4 / 2 shapes
-__host__ __device__ constexpr int next_radix(int rem)
-{
-    return (rem == 16 || rem == 4) ? 4 : (rem == 2 ? 2 : 8);
-}
+__host__ __device__ constexpr int elems_per_thread(int L) { return L < 8 ? L : 8; }
 
-template <int L, int Ns, bool INV>
-struct Stages {
-    static __device__ __forceinline__ void run(float2 *&src, float2 *&dst, int nlines, int ls)
-    {
-        if constexpr (Ns < L) {
-            constexpr int R = next_radix(L / Ns);
-            constexpr int B = L / R;  // butterflies per line
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < nlines * B; idx += blockDim.x) {
-                const int line = idx / B, j = idx - line * B;
-                stockham_stage<R, INV>(src + line * ls, dst + line * ls, L, Ns, j);
+// radix of the stage that merges sub-transforms of length Ns when rem = L/Ns
+// points remain: as large as the per-thread element count allows
+__host__ __device__ constexpr int stage_radix(int rem, int E) { return rem < E ? rem : E; }
+
+// Stages of an FFT of length L over NC lines held by one thread group:
+// v[c][q] = line c, position t + q*(L/E).  lds[c] is line c's exchange buffer
+// (lds_line(L) complex).  Every thread of the block must take part: the
+// exchange uses block barriers.
+template <int L, int E, int NC, int Ns, bool INV>
+__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
+{
+    if constexpr (Ns < L) {
+        constexpr int R = stage_radix(L / Ns, E);
+        constexpr int NB = E / R;      // butterflies per thread in this stage
+        constexpr int T = L / E;       // threads per line
+        constexpr bool last = (Ns * R == L);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int j = t + i * T;
+            const int k = j & (Ns - 1);
+            float2 w[R];
+            if constexpr (Ns > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) w[r] = twiddle<INV>(r * k, Ns * R);
             }
-            float2 *t = src;
-            src = dst;
-            dst = t;
-            Stages<L, Ns * R, INV>::run(src, dst, nlines, ls);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                float2 u[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) u[r] = v[c][i + r * NB];
+                if constexpr (Ns > 1) {
+#pragma unroll
+                    for (int r = 1; r < R; ++r) u[r] = cmul(u[r], w[r]);
+                }
+                Dft<R, INV>::run(u);
+                if constexpr (last) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[c][i + r * NB] = u[r];
+                } else {
+                    const int base = (j - k) * R + k;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) lds[c][lpad(base + r * Ns)] = u[r];
+                }
+            }
+        }
+        if constexpr (!last) {
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int q = 0; q < E; ++q) v[c][q] = lds[c][lpad(t + q * T)];
+            __syncthreads();
+            fft_stages<L, E, NC, Ns * R, INV>(v, lds, t);
         }
     }
-};
+}
 
-// FFT of `nlines` lines of length L stored in LDS at line stride `ls`,
-// ping-ponging between buffers a and b.  All threads of the block must call
-// it.  Returns the buffer holding the result (natural order), after a
-// barrier.
-template <int L, bool INV>
-__device__ __forceinline__ float2 *lds_fft(float2 *a, float2 *b, int nlines, int ls)
+// In-register FFT of NC lines per thread group (see fft_stages).  On entry
+// and exit v[c][q] holds position t + q*(L/E) of line c, natural order.
+template <int L, bool INV, int NC, int E>
+__device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
 {
-    float2 *src = a, *dst = b;
-    Stages<L, 1, INV>::run(src, dst, nlines, ls);
-    __syncthreads();
-    return src;
+    static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
+    fft_stages<L, E, NC, 1, INV>(v, lds, t);
 }
 
 }  // namespace mmk

@@ -39,7 +39,12 @@ hipError_t init_tables(hipStream_t s)
 }
 
 constexpr int kThreads = 256;
-constexpr int kLdsComplex = 4096;  // complex values per LDS buffer (32 KB)
+
+// Elements per thread in the z pass (4: fewer live registers, one more LDS
+// exchange; measured faster than 8 on the 512x512x64 padded grid).
+#ifndef MMK_ZC_E
+#define MMK_ZC_E 4
+#endif
 
 __host__ __device__ constexpr int pow2floor(int v)
 {
@@ -47,107 +52,174 @@ __host__ __device__ constexpr int pow2floor(int v)
     while (p * 2 <= v) p *= 2;
     return p;
 }
-__host__ __device__ constexpr int lines_per_block(int L, int cap)
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ constexpr int cmax(int a, int b) { return a > b ? a : b; }
+// With every axis padded to P >= 2n - 1, the non-zero inputs and the kept
+// outputs of a line all lie in its first half, which is the first half of
+// each thread's registers (q < E/2): loads and stores skip the other half,
+// and the zeros are compile-time constants for the first radix stage.
+__host__ __device__ constexpr int half_elems(int E) { return (E + 1) / 2; }
+
+__host__ __device__ constexpr int nstages(int L, int E)
 {
-    return (kLdsComplex / L) < cap ? (kLdsComplex / L) : cap;
+    int s = 0;
+    for (int n = 1; n < L; n *= stage_radix(L / n, E)) ++s;
+    return s;
 }
+
+// ---- launch shapes (shared by kernels and launchers) ----------------------
+// y passes: one line of L per T = L/E threads, 256 threads per block
+template <int L>
+struct YShape {
+    static constexpr int E = elems_per_thread(L), T = L / E, LPB = kThreads / T;
+    static constexpr int LDS = LPB * lds_line(L);
+};
+// z pass: CB columns of the three components per block
+template <int L>
+struct ZShape {
+    static constexpr int E = L < MMK_ZC_E ? L : MMK_ZC_E, T = L / E;
+    static constexpr int CBmax = cmax(1, 32768 / (3 * 8 * lds_line(L)));
+    static constexpr int CB = cmin(kThreads / T, pow2floor(CBmax));
+    static constexpr int THREADS = T * CB;
+    static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
+};
+// x passes: LPB lines of L = Px/2 complex per block (16 for 128-byte runs
+// in the transposed layout)
+template <int L>
+struct XShape {
+    static constexpr int E = elems_per_thread(L), T = L / E;
+    static constexpr int LPB = cmax(1, cmin(64, 512 / T));
+    static constexpr int THREADS = T * LPB;
+    static constexpr int LDS = LPB * lds_line(L);
+};
 
 // ------------------------------------------------------------------------
 // a1: x-forward real FFT.  A real line x[0..Px) (nx non-zeros) is packed as
 // z[k] = x[2k] + i x[2k+1], k < L = Px/2, transformed with a length-L complex
 // FFT, and unpacked with X[k] = E[k] + exp(-2 pi i k/Px) O[k],
 // E[k] = (Z[k] + conj Z[L-k])/2, O[k] = (Z[k] - conj Z[L-k])/(2i).
+// The half spectrum kx in [0, L] is written transposed, S1[c][z][kx][y].
 // ------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_xfwd(Geo g, const float *__restrict__ m,
-                                                   const float *__restrict__ ms_map, float ms,
-                                                   float2 *__restrict__ S1)
+__global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Geo g, const float *__restrict__ m,
+                                                             const float *__restrict__ ms_map, float ms,
+                                                             float2 *__restrict__ S1)
 {
-    constexpr int TL = lines_per_block(L, 64);
+    using S = XShape<L>;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
-    float2 *a = sm, *b = sm + TL * L;
-    const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * TL;
-    const int nl = min(TL, g.ny - y0);
-    const long long cell0 = ((long long)z * g.ny + y0) * g.nx;
-    const float *mrow = m + (long long)c * g.N + cell0;
-    const float *srow = ms_map ? ms_map + cell0 : nullptr;
-    for (int idx = threadIdx.x; idx < TL * L; idx += kThreads) {
-        const int t = idx / L, k = idx - t * L;
-        float2 v = make_float2(0.f, 0.f);
-        const int x0 = 2 * k;
-        if (t < nl) {
-            const long long o = (long long)t * g.nx + x0;
-            if (x0 < g.nx) v.x = (srow ? srow[o] : ms) * mrow[o];
-            if (x0 + 1 < g.nx) v.y = (srow ? srow[o + 1] : ms) * mrow[o + 1];
+    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
+    const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * LPB;
+    const int y = y0 + ll;
+    const bool ok = y < g.ny;
+    const long long cell0 = ((long long)z * g.ny + y) * g.nx;
+    const float *row = m + (long long)c * g.N + cell0;
+    float2 v[1][E];
+    const bool even = (g.nx & 1) == 0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int k = t + q * T, x0 = 2 * k;
+        float2 a = make_float2(0.f, 0.f);
+        if (q < half_elems(E) && ok && x0 < g.nx) {
+            if (even) {
+                a = *reinterpret_cast<const float2 *>(row + x0);
+                if (ms_map) {
+                    const float2 s = *reinterpret_cast<const float2 *>(ms_map + cell0 + x0);
+                    a.x *= s.x;
+                    a.y *= s.y;
+                } else {
+                    a.x *= ms;
+                    a.y *= ms;
+                }
+            } else {
+                a.x = row[x0] * (ms_map ? ms_map[cell0 + x0] : ms);
+                if (x0 + 1 < g.nx) a.y = row[x0 + 1] * (ms_map ? ms_map[cell0 + x0 + 1] : ms);
+            }
         }
-        a[idx] = v;
+        v[0][q] = a;
     }
-    const float2 *r = lds_fft<L, false>(a, b, TL, L);
+    float2 *const lds[1] = {sm + ll * LD};
+    reg_fft<L, false>(v, lds, t);
+#pragma unroll
+    for (int q = 0; q < E; ++q) sm[ll * LD + t + q * T] = v[0][q];
+    __syncthreads();
     float2 *out = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
-    for (int idx = threadIdx.x; idx < (L + 1) * TL; idx += kThreads) {
-        const int kx = idx / TL, t = idx - kx * TL;
-        if (t >= nl) continue;
-        const float2 *Z = r + t * L;
+    const int nl = min(LPB, g.ny - y0);
+    for (int idx = threadIdx.x; idx < (L + 1) * LPB; idx += S::THREADS) {
+        const int kx = idx / LPB, yl = idx - kx * LPB;
+        if (yl >= nl) continue;
+        const float2 *Z = sm + yl * LD;
         const float2 zk = Z[kx & (L - 1)];
         const float2 zc = cconj(Z[(L - kx) & (L - 1)]);
-        const float2 E = cscale(cadd(zk, zc), 0.5f);
-        const float2 O = mul_mi<false>(cscale(csub(zk, zc), 0.5f));
-        out[(long long)kx * g.ny + t] = cadd(E, cmul(twiddle<false>(kx, 2 * L), O));
+        const float2 Ev = cscale(cadd(zk, zc), 0.5f);
+        const float2 Od = mul_mi<false>(cscale(csub(zk, zc), 0.5f));
+        out[(long long)kx * g.ny + yl] = cadd(Ev, cmul(twiddle<false>(kx, 2 * L), Od));
     }
 }
 
 // ------------------------------------------------------------------------
 // a2 / a4: FFT along y of contiguous columns (length Py, ny non-zeros in /
-// ny kept out).
+// ny kept out), one column per T threads.
 // ------------------------------------------------------------------------
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_yfwd(Geo g, const float2 *__restrict__ S1,
                                                    float2 *__restrict__ S2)
 {
-    constexpr int TK = lines_per_block(L, 64);
+    using S = YShape<L>;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB;
     extern __shared__ float2 sm[];
-    float2 *a = sm, *b = sm + TK * L;
-    const int c = blockIdx.z, z = blockIdx.y, k0 = blockIdx.x * TK;
-    const int nk = min(TK, g.Hx - k0);
-    const long long col0 = (long long)(c * g.nz + z) * g.Hx + k0;
-    const float2 *in = S1 + col0 * g.ny;
-    for (int idx = threadIdx.x; idx < TK * L; idx += kThreads) {
-        const int t = idx / L, y = idx - t * L;
-        a[idx] = (t < nk && y < g.ny) ? in[(long long)t * g.ny + y] : make_float2(0.f, 0.f);
+    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
+    const long long line = (long long)blockIdx.x * LPB + ll;
+    const bool ok = line < 3LL * g.nz * g.Hx;
+    const float2 *in = S1 + line * g.ny;
+    float2 v[1][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int y = t + q * T;
+        v[0][q] = (q < half_elems(E) && ok && y < g.ny) ? in[y] : make_float2(0.f, 0.f);
     }
-    const float2 *r = lds_fft<L, false>(a, b, TK, L);
-    float2 *out = S2 + col0 * L;
-    for (int idx = threadIdx.x; idx < nk * L; idx += kThreads) out[idx] = r[idx];
+    float2 *const lds[1] = {sm + ll * lds_line(L)};
+    reg_fft<L, false>(v, lds, t);
+    if (ok) {
+        float2 *out = S2 + line * L;
+#pragma unroll
+        for (int q = 0; q < E; ++q) out[t + q * T] = v[0][q];
+    }
 }
 
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_yinv(Geo g, const float2 *__restrict__ S2,
                                                    float2 *__restrict__ S1)
 {
-    constexpr int TK = lines_per_block(L, 64);
+    using S = YShape<L>;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB;
     extern __shared__ float2 sm[];
-    float2 *a = sm, *b = sm + TK * L;
-    const int c = blockIdx.z, z = blockIdx.y, k0 = blockIdx.x * TK;
-    const int nk = min(TK, g.Hx - k0);
-    const long long col0 = (long long)(c * g.nz + z) * g.Hx + k0;
-    const float2 *in = S2 + col0 * L;
-    for (int idx = threadIdx.x; idx < TK * L; idx += kThreads)
-        a[idx] = idx < nk * L ? in[idx] : make_float2(0.f, 0.f);
-    const float2 *r = lds_fft<L, true>(a, b, TK, L);
-    float2 *out = S1 + col0 * g.ny;
-    for (int idx = threadIdx.x; idx < TK * g.ny; idx += kThreads) {
-        const int t = idx / g.ny, y = idx - t * g.ny;
-        if (t < nk) out[(long long)t * g.ny + y] = r[t * L + y];
+    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
+    const long long line = (long long)blockIdx.x * LPB + ll;
+    const bool ok = line < 3LL * g.nz * g.Hx;
+    const float2 *in = S2 + line * L;
+    float2 v[1][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[0][q] = ok ? in[t + q * T] : make_float2(0.f, 0.f);
+    float2 *const lds[1] = {sm + ll * lds_line(L)};
+    reg_fft<L, true>(v, lds, t);
+    if (ok) {
+        float2 *out = S1 + line * g.ny;
+#pragma unroll
+        for (int q = 0; q < half_elems(E); ++q) {
+            const int y = t + q * T;
+            if (y < g.ny) out[y] = v[0][q];
+        }
     }
 }
 
 // ------------------------------------------------------------------------
 // a3: z transform + tensor multiply + inverse z transform, per (kx, ky).
 // K holds the octant kx in [0,Hx), ky in [0,Hy), kz in [0,Hz) as
-// K[kx][ky][kz][6] (xx, yy, zz, xy, xz, yz).  Components odd in y (xy, yz)
-// change sign for ky > Py/2, components odd in z (xz, yz) for kz > Pz/2.
-// Compensated form: each of the six real dot products of three terms is
-// accumulated with an error-free product (fma) and two-sum and rounded once.
+// K[kx][kz][comp][ky], comp = xx, yy, zz, xy, xz, yz.  Components odd in y
+// (xy, yz) change sign for ky > Py/2, components odd in z (xz, yz) for
+// kz > Pz/2.  Compensated form: each of the six real dot products of three
+// terms is accumulated error-free (fma products, two-sum) and rounded once.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 {
@@ -175,60 +247,67 @@ __device__ __forceinline__ float dot3_comp(float k0, float x0, float k1, float x
 }
 
 template <int L, bool COMP>
-__global__ __launch_bounds__(kThreads) void k_zconv(Geo g, float2 *__restrict__ S2,
-                                                    const float *__restrict__ K)
+__global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Geo g, float2 *__restrict__ S2,
+                                                              const float *__restrict__ K)
 {
-    constexpr int TYr = pow2floor(1365 / L);
-    constexpr int TY = TYr > 256 ? 256 : (TYr < 1 ? 1 : TYr);
+    using S = ZShape<L>;
+    constexpr int E = S::E, T = S::T, CB = S::CB;
     extern __shared__ float2 sm[];
-    float2 *a = sm, *b = sm + 3 * TY * L;
-    const int kx = blockIdx.y, ky0 = blockIdx.x * TY;
-    const int nyl = min(TY, g.Py - ky0);
+    const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
+    const int kx = blockIdx.y, ky = blockIdx.x * CB + col;
+    const bool ok = ky < g.Py;
     const long long plane = (long long)g.Hx * g.Py;  // stride between z planes
-    float2 *base = S2 + (long long)kx * g.Py + ky0;
-    for (int idx = threadIdx.x; idx < 3 * TY * L; idx += kThreads) {
-        const int t = idx % TY, rest = idx / TY;
-        const int zz = rest % L, c = rest / L;
-        float2 v = make_float2(0.f, 0.f);
-        if (t < nyl && zz < g.nz) v = base[((long long)c * g.nz + zz) * plane + t];
-        a[(c * TY + t) * L + zz] = v;
-    }
-    float2 *r = lds_fft<L, false>(a, b, 3 * TY, L);
-    float2 *o = (r == a) ? b : a;
+    float2 *base = S2 + (long long)kx * g.Py + ky;
+    float2 v[3][E];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int zz = t + q * T;
+            v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[((long long)c * g.nz + zz) * plane]
+                                                           : make_float2(0.f, 0.f);
+        }
+    float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
+                            sm + (2 * CB + col) * lds_line(L)};
+    reg_fft<L, false>(v, lds, t);
     const int hy = g.Py / 2, hz = g.Pz / 2;
-    for (int idx = threadIdx.x; idx < TY * L; idx += kThreads) {
-        const int kz = idx / TY, t = idx - kz * TY;
-        if (t >= nyl) continue;
-        const int ky = ky0 + t;
-        const bool fy = ky > hy, fz = kz > hz;
-        const int kyf = fy ? g.Py - ky : ky, kzf = fz ? g.Pz - kz : kz;
-        const float *k6 = K + (((long long)kx * g.Hy + kyf) * g.Hz + kzf) * 6;
-        const float sy = fy ? -1.f : 1.f, sz = fz ? -1.f : 1.f;
+    const bool fy = ky > hy;
+    const int kyf = fy ? g.Py - ky : ky;
+    const float sy = fy ? -1.f : 1.f;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int kz = t + q * T;
+        const bool fz = kz > hz;
+        const int kzf = fz ? g.Pz - kz : kz;
+        const float sz = fz ? -1.f : 1.f;
+        float k6[6] = {0, 0, 0, 0, 0, 0};
+        if (ok) {
+            const float *kp = K + ((long long)kx * g.Hz + kzf) * 6 * g.Hy + kyf;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) k6[p] = kp[(long long)p * g.Hy];
+        }
         const float kxx = k6[0], kyy = k6[1], kzz = k6[2];
         const float kxy = sy * k6[3], kxz = sz * k6[4], kyz = sy * sz * k6[5];
-        float2 *px = r + (0 * TY + t) * L + kz;
-        float2 *py = r + (1 * TY + t) * L + kz;
-        float2 *pz = r + (2 * TY + t) * L + kz;
-        const float2 mx = *px, my = *py, mz = *pz;
-        float2 hx, hy2, hz2;
+        const float2 mx = v[0][q], my = v[1][q], mz = v[2][q];
         if (COMP) {
-            hx = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
-            hy2 = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
-            hz2 = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
+            v[0][q] = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
+            v[1][q] = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
+            v[2][q] = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
         } else {
-            hx = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
-            hy2 = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
-            hz2 = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
+            v[0][q] = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
+            v[1][q] = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
+            v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
         }
-        *px = hx;
-        *py = hy2;
-        *pz = hz2;
     }
-    const float2 *q = lds_fft<L, true>(r, o, 3 * TY, L);
-    for (int idx = threadIdx.x; idx < 3 * TY * g.nz; idx += kThreads) {
-        const int t = idx % TY, rest = idx / TY;
-        const int zz = rest % g.nz, c = rest / g.nz;
-        if (t < nyl) base[((long long)c * g.nz + zz) * plane + t] = q[(c * TY + t) * L + zz];
+    reg_fft<L, true>(v, lds, t);
+    if (ok) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < half_elems(E); ++q) {
+                const int zz = t + q * T;
+                if (zz < g.nz) base[((long long)c * g.nz + zz) * plane] = v[c][q];
+            }
     }
 }
 
@@ -239,43 +318,51 @@ __global__ __launch_bounds__(kThreads) void k_zconv(Geo g, float2 *__restrict__ 
 // x[2n] + i x[2n+1].
 // ------------------------------------------------------------------------
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_xinv(Geo g, const float2 *__restrict__ S1,
-                                                   float *__restrict__ Hd)
+__global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Geo g, const float2 *__restrict__ S1,
+                                                             float *__restrict__ Hd)
 {
-    constexpr int TL = lines_per_block(L, 64);
+    using S = XShape<L>;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
-    float2 *a = sm, *b = sm + TL * L;
-    const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * TL;
-    const int nl = min(TL, g.ny - y0);
+    const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * LPB;
+    const int nl = min(LPB, g.ny - y0);
     const float2 *in = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
-    // pairs (k, L-k) for k in [0, L/2]; k = 0 pairs X[0] with X[L]
-    constexpr int HP = L / 2 + 1;
-    for (int idx = threadIdx.x; idx < HP * TL; idx += kThreads) {
-        const int k = idx / TL, t = idx - k * TL;
-        float2 xk = make_float2(0.f, 0.f), xl = make_float2(0.f, 0.f);
-        if (t < nl) {
-            xk = in[(long long)k * g.ny + t];
-            xl = in[(long long)(L - k) * g.ny + t];
-        }
-        {
-            const float2 xc = cconj(xl);
-            const float2 E = cadd(xk, xc);
-            const float2 O = cmul(csub(xk, xc), twiddle<true>(k, 2 * L));
-            a[t * L + (k & (L - 1))] = cadd(E, mul_mi<true>(O));
-        }
-        if (k > 0 && 2 * k < L) {
-            const float2 xc = cconj(xk);
-            const float2 E = cadd(xl, xc);
-            const float2 O = cmul(csub(xl, xc), twiddle<true>(L - k, 2 * L));
-            a[t * L + (L - k)] = cadd(E, mul_mi<true>(O));
+    for (int idx = threadIdx.x; idx < (L + 1) * LPB; idx += S::THREADS) {
+        const int kx = idx / LPB, yl = idx - kx * LPB;
+        sm[yl * LD + kx] = yl < nl ? in[(long long)kx * g.ny + yl] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
+    float2 v[1][E];
+    {
+        const float2 *X = sm + ll * LD;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int k = t + q * T;
+            const float2 xk = X[k], xc = cconj(X[L - k]);
+            const float2 Ev = cadd(xk, xc);
+            const float2 Od = cmul(csub(xk, xc), twiddle<true>(k, 2 * L));
+            v[0][q] = cadd(Ev, mul_mi<true>(Od));
         }
     }
-    const float2 *r = lds_fft<L, true>(a, b, TL, L);
-    float *out = Hd + (long long)c * g.N + ((long long)z * g.ny + y0) * g.nx;
-    for (int idx = threadIdx.x; idx < nl * g.nx; idx += kThreads) {
-        const int t = idx / g.nx, x = idx - t * g.nx;
-        const float2 v = r[t * L + (x >> 1)];
-        out[(long long)t * g.nx + x] = (x & 1) ? v.y : v.x;
+    __syncthreads();
+    float2 *const lds[1] = {sm + ll * LD};
+    reg_fft<L, true>(v, lds, t);
+    if (ll < nl) {
+        float *out = Hd + (long long)c * g.N + ((long long)z * g.ny + y0 + ll) * g.nx;
+        const bool even = (g.nx & 1) == 0;
+#pragma unroll
+        for (int q = 0; q < half_elems(E); ++q) {
+            const int x0 = 2 * (t + q * T);
+            if (x0 < g.nx) {
+                if (even) {
+                    *reinterpret_cast<float2 *>(out + x0) = v[0][q];
+                } else {
+                    out[x0] = v[0][q].x;
+                    if (x0 + 1 < g.nx) out[x0 + 1] = v[0][q].y;
+                }
+            }
+        }
     }
 }
 
@@ -285,14 +372,205 @@ __global__ __launch_bounds__(kThreads) void k_xinv(Geo g, const float2 *__restri
 //   f = c1 m x H + c2 m x (m x H),  c1 = -gamma0/(1+alpha^2), c2 = alpha c1
 //   m' = m + dt f, then m' /= |m'| unless renormalisation is off.
 // Free (Neumann) boundaries: a missing neighbour contributes nothing.
+// V cells along x per thread (4 with 16-byte accesses when nx % 4 == 0).
 // ------------------------------------------------------------------------
-template <int MODE>
+template <int V>
+struct VecT;
+template <>
+struct VecT<1> {
+    using T = float;
+};
+template <>
+struct VecT<4> {
+    using T = float4;
+};
+
+template <int V>
+__device__ __forceinline__ void vload(const float *p, float (&o)[V])
+{
+    if constexpr (V == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(p);
+        o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+    } else {
+        o[0] = *p;
+    }
+}
+template <int V>
+__device__ __forceinline__ void vstore(float *p, const float (&o)[V])
+{
+    if constexpr (V == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    } else {
+        *p = o[0];
+    }
+}
+
+template <int MODE, int V>
 __global__ __launch_bounds__(kThreads) void k_local(Geo g, LocalParams p, const float *__restrict__ m,
                                                     const float *__restrict__ Hd,
                                                     const float *__restrict__ ms_map,
                                                     const float *__restrict__ h_map, uint32_t terms,
                                                     float dt, int renorm, float *__restrict__ out_m,
                                                     float *__restrict__ out_h, int *__restrict__ flag)
+{
+    const long long i0 = ((long long)blockIdx.x * kThreads + threadIdx.x) * V;
+    if (i0 >= g.N) return;
+    const long long N = g.N;
+    const int x0 = (int)(i0 % g.nx);
+    const long long r = i0 / g.nx;
+    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+    float mc[3][V], h[3][V];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        vload<V>(m + c * N + i0, mc[c]);
+        if ((terms & 2u) && Hd) {
+            vload<V>(Hd + c * N + i0, h[c]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) h[c][j] = 0.f;
+        }
+    }
+    float inv_ms[V];
+    if (ms_map) {
+        float s[V];
+        vload<V>(ms_map + i0, s);
+#pragma unroll
+        for (int j = 0; j < V; ++j) inv_ms[j] = 1.0f / s[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < V; ++j) inv_ms[j] = 1.0f / p.ms;
+    }
+    if (terms & 1u) {
+        float lap[3][V];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < V; ++j) lap[c][j] = 0.f;
+        // x neighbours: inside the vector, plus one scalar on each side
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float left = x0 > 0 ? m[c * N + i0 - 1] : 0.f;
+            const float right = x0 + V < g.nx ? m[c * N + i0 + V] : 0.f;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                const float a = mc[c][j];
+                float s = 0.f;
+                if (j > 0) s += mc[c][j - 1] - a;
+                else if (x0 > 0) s += left - a;
+                if (j < V - 1) s += mc[c][j + 1] - a;
+                else if (x0 + V < g.nx) s += right - a;
+                lap[c][j] = p.ax * s;
+            }
+        }
+        const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+        auto add = [&](long long off, float w) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float nb[V];
+                vload<V>(m + c * N + i0 + off, nb);
+#pragma unroll
+                for (int j = 0; j < V; ++j) lap[c][j] = fmaf(w, nb[j] - mc[c][j], lap[c][j]);
+            }
+        };
+        if (y > 0) add(-sy, p.ay);
+        if (y < g.ny - 1) add(sy, p.ay);
+        if (z > 0) add(-sz, p.az);
+        if (z < g.nz - 1) add(sz, p.az);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int j = 0; j < V; ++j) h[c][j] = fmaf(lap[c][j], inv_ms[j], h[c][j]);
+    }
+    if (terms & 4u) {
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const float k = p.ku2 * inv_ms[j] * (mc[0][j] * p.u0 + mc[1][j] * p.u1 + mc[2][j] * p.u2);
+            h[0][j] = fmaf(k, p.u0, h[0][j]);
+            h[1][j] = fmaf(k, p.u1, h[1][j]);
+            h[2][j] = fmaf(k, p.u2, h[2][j]);
+        }
+    }
+    if (terms & 8u) {
+        if (h_map) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float e[V];
+                vload<V>(h_map + c * N + i0, e);
+#pragma unroll
+                for (int j = 0; j < V; ++j) h[c][j] += e[j];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                h[0][j] += p.h0;
+                h[1][j] += p.h1;
+                h[2][j] += p.h2;
+            }
+        }
+    }
+    if (MODE == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vstore<V>(out_h + c * N + i0, h[c]);
+        return;
+    }
+    float o[3][V];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
+        const float hx = h[0][j], hy = h[1][j], hz = h[2][j];
+        // m x H and m x (m x H)
+        const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
+        const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
+        float nx_ = mx + dt * (p.c1 * ax + p.c2 * bx);
+        float ny_ = my + dt * (p.c1 * ay + p.c2 * by);
+        float nz_ = mz + dt * (p.c1 * az + p.c2 * bz);
+        if (renorm) {
+            const float s = rsqrtf(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+            nx_ *= s;
+            ny_ *= s;
+            nz_ *= s;
+        }
+        bad |= !(isfinite(nx_) && isfinite(ny_) && isfinite(nz_));
+        o[0][j] = nx_;
+        o[1][j] = ny_;
+        o[2][j] = nz_;
+    }
+    if (bad) *flag = 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vstore<V>(out_m + c * N + i0, o[c]);
+}
+
+// ------------------------------------------------------------------------
+// Adjoint of one Euler step (exact transpose of the discrete step above).
+// Forward: H = H_demag(m) + H_ex(m) + H_an(m) + h_ext; f = c1 m x H +
+// c2 m x (m x H); v = m + dt f; m' = v/|v|.  Given lam' = dL/dm':
+//   w   = (lam' - (m'.lam') m')/|v|            (lam' without renormalisation)
+//   g_H = dt [c1 (w x m) + c2 m x (m x w)]     (= (df/dH)^T w dt)
+//   lam = w + dt [c1 H x w + c2 ((m x H) x w + H x (w x m))]
+//         + (2A/mu0) L(g_H/Ms) - Ms (N * g_H) + (2Ku/(mu0 Ms)) (u.g_H) u
+//   dL/dh_ext += g_H
+//   dL/dMs    += -(H_ex + H_an).g_H / Ms - m.(N * g_H)
+// L is the symmetric Neumann Laplacian, N* the demag convolution, which is
+// self-adjoint (N(-r) = N(r), each N symmetric), so N * g_H is the forward
+// demag pipeline run on g_H with unit Ms (it returns -N * g_H).
+// k_adj_a does everything except the two non-local terms; k_adj_b adds them.
+// ------------------------------------------------------------------------
+__device__ __forceinline__ void cross3f(float ax, float ay, float az, float bx, float by, float bz, float &cx,
+                                        float &cy, float &cz)
+{
+    cx = ay * bz - az * by;
+    cy = az * bx - ax * bz;
+    cz = ax * by - ay * bx;
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_a(Geo g, LocalParams p, const float *__restrict__ m,
+                                                    const float *__restrict__ Hd,
+                                                    const float *__restrict__ ms_map,
+                                                    const float *__restrict__ h_map,
+                                                    const float *__restrict__ lam1, float dt, int renorm,
+                                                    float *__restrict__ gH, float *__restrict__ lam_loc,
+                                                    float *__restrict__ g_hext, float *__restrict__ g_ms)
 {
     const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (i >= g.N) return;
@@ -301,21 +579,16 @@ __global__ __launch_bounds__(kThreads) void k_local(Geo g, LocalParams p, const 
     const long long r = i / g.nx;
     const int y = (int)(r % g.ny), z = (int)(r / g.ny);
     const float mx = m[i], my = m[N + i], mz = m[2 * N + i];
-    float hx = 0.f, hy = 0.f, hz = 0.f;
-    if ((terms & 2u) && Hd) {
-        hx = Hd[i];
-        hy = Hd[N + i];
-        hz = Hd[2 * N + i];
-    }
     const float ms = ms_map ? ms_map[i] : p.ms;
     const float inv_ms = 1.0f / ms;
-    if (terms & 1u) {
-        float lx = 0.f, ly = 0.f, lz = 0.f;
+    // exchange and anisotropy fields (kept apart for dL/dMs)
+    float ex = 0.f, ey = 0.f, ez = 0.f;
+    {
         const long long sy = g.nx, sz = (long long)g.nx * g.ny;
         auto add = [&](long long j, float w) {
-            lx = fmaf(w, m[j] - mx, lx);
-            ly = fmaf(w, m[N + j] - my, ly);
-            lz = fmaf(w, m[2 * N + j] - mz, lz);
+            ex = fmaf(w, m[j] - mx, ex);
+            ey = fmaf(w, m[N + j] - my, ey);
+            ez = fmaf(w, m[2 * N + j] - mz, ez);
         };
         if (x > 0) add(i - 1, p.ax);
         if (x < g.nx - 1) add(i + 1, p.ax);
@@ -323,49 +596,102 @@ __global__ __launch_bounds__(kThreads) void k_local(Geo g, LocalParams p, const 
         if (y < g.ny - 1) add(i + sy, p.ay);
         if (z > 0) add(i - sz, p.az);
         if (z < g.nz - 1) add(i + sz, p.az);
-        hx = fmaf(lx, inv_ms, hx);
-        hy = fmaf(ly, inv_ms, hy);
-        hz = fmaf(lz, inv_ms, hz);
+        ex *= inv_ms;
+        ey *= inv_ms;
+        ez *= inv_ms;
     }
-    if (terms & 4u) {
-        const float k = p.ku2 * inv_ms * (mx * p.u0 + my * p.u1 + mz * p.u2);
-        hx = fmaf(k, p.u0, hx);
-        hy = fmaf(k, p.u1, hy);
-        hz = fmaf(k, p.u2, hz);
+    const float mu = mx * p.u0 + my * p.u1 + mz * p.u2;
+    const float ka = p.ku2 * inv_ms;
+    const float anx = ka * mu * p.u0, any = ka * mu * p.u1, anz = ka * mu * p.u2;
+    float hx = Hd[i] + ex + anx, hy = Hd[N + i] + ey + any, hz = Hd[2 * N + i] + ez + anz;
+    if (h_map) {
+        hx += h_map[i];
+        hy += h_map[N + i];
+        hz += h_map[2 * N + i];
+    } else {
+        hx += p.h0;
+        hy += p.h1;
+        hz += p.h2;
     }
-    if (terms & 8u) {
-        if (h_map) {
-            hx += h_map[i];
-            hy += h_map[N + i];
-            hz += h_map[2 * N + i];
-        } else {
-            hx += p.h0;
-            hy += p.h1;
-            hz += p.h2;
-        }
-    }
-    if (MODE == 0) {
-        out_h[i] = hx;
-        out_h[N + i] = hy;
-        out_h[2 * N + i] = hz;
-        return;
-    }
-    // m x H and m x (m x H)
-    const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
-    const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
-    float nx_ = mx + dt * (p.c1 * ax + p.c2 * bx);
-    float ny_ = my + dt * (p.c1 * ay + p.c2 * by);
-    float nz_ = mz + dt * (p.c1 * az + p.c2 * bz);
+    // forward step, recomputed
+    float ax, ay, az, bx, by, bz;
+    cross3f(mx, my, mz, hx, hy, hz, ax, ay, az);  // m x H
+    cross3f(mx, my, mz, ax, ay, az, bx, by, bz);  // m x (m x H)
+    const float vx = mx + dt * (p.c1 * ax + p.c2 * bx);
+    const float vy = my + dt * (p.c1 * ay + p.c2 * by);
+    const float vz = mz + dt * (p.c1 * az + p.c2 * bz);
+    float wx = lam1[i], wy = lam1[N + i], wz = lam1[2 * N + i];
     if (renorm) {
-        const float s = rsqrtf(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
-        nx_ *= s;
-        ny_ *= s;
-        nz_ *= s;
+        const float inv = rsqrtf(vx * vx + vy * vy + vz * vz);
+        const float px = vx * inv, py = vy * inv, pz = vz * inv;
+        const float d = px * wx + py * wy + pz * wz;
+        wx = (wx - d * px) * inv;
+        wy = (wy - d * py) * inv;
+        wz = (wz - d * pz) * inv;
     }
-    if (!(isfinite(nx_) && isfinite(ny_) && isfinite(nz_))) *flag = 1;
-    out_m[i] = nx_;
-    out_m[N + i] = ny_;
-    out_m[2 * N + i] = nz_;
+    // g_H = dt [c1 (w x m) + c2 m x (m x w)]
+    float wmx, wmy, wmz, mwx, mwy, mwz, mmwx, mmwy, mmwz;
+    cross3f(wx, wy, wz, mx, my, mz, wmx, wmy, wmz);
+    cross3f(mx, my, mz, wx, wy, wz, mwx, mwy, mwz);
+    cross3f(mx, my, mz, mwx, mwy, mwz, mmwx, mmwy, mmwz);
+    const float gx = dt * (p.c1 * wmx + p.c2 * mmwx);
+    const float gy = dt * (p.c1 * wmy + p.c2 * mmwy);
+    const float gz = dt * (p.c1 * wmz + p.c2 * mmwz);
+    // lam_loc = w + dt [c1 H x w + c2 ((m x H) x w + H x (w x m))] + aniso^T g_H
+    float hwx, hwy, hwz, mhwx, mhwy, mhwz, hwmx, hwmy, hwmz;
+    cross3f(hx, hy, hz, wx, wy, wz, hwx, hwy, hwz);
+    cross3f(ax, ay, az, wx, wy, wz, mhwx, mhwy, mhwz);
+    cross3f(hx, hy, hz, wmx, wmy, wmz, hwmx, hwmy, hwmz);
+    const float ug = p.u0 * gx + p.u1 * gy + p.u2 * gz;
+    lam_loc[i] = wx + dt * (p.c1 * hwx + p.c2 * (mhwx + hwmx)) + ka * ug * p.u0;
+    lam_loc[N + i] = wy + dt * (p.c1 * hwy + p.c2 * (mhwy + hwmy)) + ka * ug * p.u1;
+    lam_loc[2 * N + i] = wz + dt * (p.c1 * hwz + p.c2 * (mhwz + hwmz)) + ka * ug * p.u2;
+    gH[i] = gx;
+    gH[N + i] = gy;
+    gH[2 * N + i] = gz;
+    if (g_hext) {
+        g_hext[i] += gx;
+        g_hext[N + i] += gy;
+        g_hext[2 * N + i] += gz;
+    }
+    if (g_ms) g_ms[i] -= ((ex + anx) * gx + (ey + any) * gy + (ez + anz) * gz) * inv_ms;
+}
+
+// lam = lam_loc + (2A/mu0) L(g_H/Ms) + Ms D,  dL/dMs += m.D,  D = -(N * g_H)
+__global__ __launch_bounds__(kThreads) void k_adj_b(Geo g, LocalParams p, const float *__restrict__ m,
+                                                    const float *__restrict__ gH, const float *__restrict__ D,
+                                                    const float *__restrict__ ms_map,
+                                                    const float *__restrict__ lam_loc, float *__restrict__ lam,
+                                                    float *__restrict__ g_ms)
+{
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= g.N) return;
+    const long long N = g.N;
+    const int x = (int)(i % g.nx);
+    const long long r = i / g.nx;
+    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+    const float ms = ms_map ? ms_map[i] : p.ms;
+    const float inv_ms = 1.0f / ms;
+    const float qx = gH[i] * inv_ms, qy = gH[N + i] * inv_ms, qz = gH[2 * N + i] * inv_ms;
+    float lx = 0.f, ly = 0.f, lz = 0.f;
+    const long long sy = g.nx, sz = (long long)g.nx * g.ny;
+    auto add = [&](long long j, float w) {
+        const float inv_j = ms_map ? 1.0f / ms_map[j] : inv_ms;
+        lx = fmaf(w, gH[j] * inv_j - qx, lx);
+        ly = fmaf(w, gH[N + j] * inv_j - qy, ly);
+        lz = fmaf(w, gH[2 * N + j] * inv_j - qz, lz);
+    };
+    if (x > 0) add(i - 1, p.ax);
+    if (x < g.nx - 1) add(i + 1, p.ax);
+    if (y > 0) add(i - sy, p.ay);
+    if (y < g.ny - 1) add(i + sy, p.ay);
+    if (z > 0) add(i - sz, p.az);
+    if (z < g.nz - 1) add(i + sz, p.az);
+    const float dx = D[i], dy = D[N + i], dz = D[2 * N + i];
+    lam[i] = lam_loc[i] + lx + ms * dx;
+    lam[N + i] = lam_loc[N + i] + ly + ms * dy;
+    lam[2 * N + i] = lam_loc[2 * N + i] + lz + ms * dz;
+    if (g_ms) g_ms[i] += m[i] * dx + m[N + i] * dy + m[2 * N + i] * dz;
 }
 
 // ------------------------------------------------------------------------
@@ -632,11 +958,11 @@ __global__ __launch_bounds__(kThreads) void k_pack(Geo g, const double *__restri
     const long long total = (long long)g.Hx * g.Hy * g.Hz;
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= total) return;
-    // T is [Hz][Hy][Hx]; K is [Hx][Hy][Hz][6]
+    // T is [Hz][Hy][Hx]; K is [Hx][Hz][6][Hy]
     const int kx = (int)(idx % g.Hx);
     const long long r = idx / g.Hx;
     const int ky = (int)(r % g.Hy), kz = (int)(r / g.Hy);
-    K[(((long long)kx * g.Hy + ky) * g.Hz + kz) * 6 + comp] = (float)(scale * T[idx]);
+    K[(((long long)kx * g.Hz + kz) * 6 + comp) * g.Hy + ky] = (float)(scale * T[idx]);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -645,17 +971,16 @@ __global__ __launch_bounds__(kThreads) void k_pack(Geo g, const double *__restri
 
 hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s)
 {
-    const int L = g.Px / 2;
-    switch (L) {
-#define CASE(LL)                                                                          \
-    case LL: {                                                                            \
-        if constexpr (LL <= 512) {                                                        \
-            constexpr int TL = lines_per_block(LL, 64);                                   \
-            dim3 grid((g.ny + TL - 1) / TL, g.nz, 3);                                     \
-            hipLaunchKernelGGL(k_xfwd<LL>, grid, dim3(kThreads), 2 * TL * LL * sizeof(float2), s, \
-                               g, m, ms_map, ms, S1);                                     \
-        }                                                                                 \
-        break;                                                                            \
+    switch (g.Px / 2) {
+#define CASE(LL)                                                                                  \
+    case LL: {                                                                                    \
+        if constexpr (LL <= 512) {                                                                \
+            using S = XShape<LL>;                                                                 \
+            dim3 grid((g.ny + S::LPB - 1) / S::LPB, g.nz, 3);                                     \
+            hipLaunchKernelGGL(k_xfwd<LL>, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, g, m, \
+                               ms_map, ms, S1);                                                   \
+        }                                                                                         \
+        break;                                                                                    \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -667,17 +992,15 @@ hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float 
 
 hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
 {
-    const int L = g.Px / 2;
-    switch (L) {
-#define CASE(LL)                                                                          \
-    case LL: {                                                                            \
-        if constexpr (LL <= 512) {                                                        \
-            constexpr int TL = lines_per_block(LL, 64);                                   \
-            dim3 grid((g.ny + TL - 1) / TL, g.nz, 3);                                     \
-            hipLaunchKernelGGL(k_xinv<LL>, grid, dim3(kThreads), 2 * TL * LL * sizeof(float2), s, \
-                               g, S1, Hd);                                                \
-        }                                                                                 \
-        break;                                                                            \
+    switch (g.Px / 2) {
+#define CASE(LL)                                                                                  \
+    case LL: {                                                                                    \
+        if constexpr (LL <= 512) {                                                                \
+            using S = XShape<LL>;                                                                 \
+            dim3 grid((g.ny + S::LPB - 1) / S::LPB, g.nz, 3);                                     \
+            hipLaunchKernelGGL(k_xinv<LL>, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, g, S1, Hd); \
+        }                                                                                         \
+        break;                                                                                    \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -689,14 +1012,14 @@ hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
 
 hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s)
 {
+    const long long lines = 3LL * g.nz * g.Hx;
     switch (g.Py) {
-#define CASE(LL)                                                                          \
-    case LL: {                                                                            \
-        constexpr int TK = lines_per_block(LL, 64);                                       \
-        dim3 grid((g.Hx + TK - 1) / TK, g.nz, 3);                                         \
-        hipLaunchKernelGGL(k_yfwd<LL>, grid, dim3(kThreads), 2 * TK * LL * sizeof(float2), s, g, \
-                           S1, S2);                                                       \
-        break;                                                                            \
+#define CASE(LL)                                                                                  \
+    case LL: {                                                                                    \
+        using S = YShape<LL>;                                                                     \
+        dim3 grid((unsigned)((lines + S::LPB - 1) / S::LPB));                                    \
+        hipLaunchKernelGGL(k_yfwd<LL>, grid, dim3(kThreads), S::LDS * sizeof(float2), s, g, S1, S2); \
+        break;                                                                                    \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -708,14 +1031,14 @@ hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s
 
 hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s)
 {
+    const long long lines = 3LL * g.nz * g.Hx;
     switch (g.Py) {
-#define CASE(LL)                                                                          \
-    case LL: {                                                                            \
-        constexpr int TK = lines_per_block(LL, 64);                                       \
-        dim3 grid((g.Hx + TK - 1) / TK, g.nz, 3);                                         \
-        hipLaunchKernelGGL(k_yinv<LL>, grid, dim3(kThreads), 2 * TK * LL * sizeof(float2), s, g, \
-                           S2, S1);                                                       \
-        break;                                                                            \
+#define CASE(LL)                                                                                  \
+    case LL: {                                                                                    \
+        using S = YShape<LL>;                                                                     \
+        dim3 grid((unsigned)((lines + S::LPB - 1) / S::LPB));                                    \
+        hipLaunchKernelGGL(k_yinv<LL>, grid, dim3(kThreads), S::LDS * sizeof(float2), s, g, S2, S1); \
+        break;                                                                                    \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -728,17 +1051,16 @@ hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s
 hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s)
 {
     switch (g.Pz) {
-#define CASE(LL)                                                                          \
-    case LL: {                                                                            \
-        constexpr int TYr = pow2floor(1365 / LL);                                         \
-        constexpr int TY = TYr > 256 ? 256 : (TYr < 1 ? 1 : TYr);                         \
-        dim3 grid((g.Py + TY - 1) / TY, g.Hx, 1);                                         \
-        const size_t lds = 2 * 3 * TY * LL * sizeof(float2);                              \
-        if (comp)                                                                         \
-            hipLaunchKernelGGL((k_zconv<LL, true>), grid, dim3(kThreads), lds, s, g, S2, K); \
-        else                                                                              \
-            hipLaunchKernelGGL((k_zconv<LL, false>), grid, dim3(kThreads), lds, s, g, S2, K); \
-        break;                                                                            \
+#define CASE(LL)                                                                                  \
+    case LL: {                                                                                    \
+        using S = ZShape<LL>;                                                                     \
+        dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, 1);                                           \
+        const size_t lds = S::LDS * sizeof(float2);                                               \
+        if (comp)                                                                                 \
+            hipLaunchKernelGGL((k_zconv<LL, true>), grid, dim3(S::THREADS), lds, s, g, S2, K);    \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_zconv<LL, false>), grid, dim3(S::THREADS), lds, s, g, S2, K);   \
+        break;                                                                                    \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -752,13 +1074,36 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
                         const float *ms_map, const float *h_map, uint32_t terms, int mode, float dt,
                         int renorm, float *out_m, float *out_h, int *flag, hipStream_t s)
 {
+    const bool vec = (g.nx % 4) == 0;
+    const long long items = vec ? g.N / 4 : g.N;
+    dim3 grid((unsigned)((items + kThreads - 1) / kThreads));
+#define LOCAL(MODE, V)                                                                            \
+    hipLaunchKernelGGL((k_local<MODE, V>), grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, terms, dt, \
+                       renorm, out_m, out_h, flag)
+    if (mode == 0) {
+        if (vec) LOCAL(0, 4); else LOCAL(0, 1);
+    } else {
+        if (vec) LOCAL(1, 4); else LOCAL(1, 1);
+    }
+#undef LOCAL
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
+                        const float *h_map, const float *lam1, float dt, int renorm, float *gH, float *lam_loc,
+                        float *g_hext, float *g_ms, hipStream_t s)
+{
     dim3 grid((unsigned)((g.N + kThreads - 1) / kThreads));
-    if (mode == 0)
-        hipLaunchKernelGGL(k_local<0>, grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, terms, dt,
-                           renorm, out_m, out_h, flag);
-    else
-        hipLaunchKernelGGL(k_local<1>, grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, terms, dt,
-                           renorm, out_m, out_h, flag);
+    hipLaunchKernelGGL(k_adj_a, grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, lam1, dt, renorm, gH,
+                       lam_loc, g_hext, g_ms);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_b(const Geo &g, const LocalParams &p, const float *m, const float *gH, const float *D,
+                        const float *ms_map, const float *lam_loc, float *lam, float *g_ms, hipStream_t s)
+{
+    dim3 grid((unsigned)((g.N + kThreads - 1) / kThreads));
+    hipLaunchKernelGGL(k_adj_b, grid, dim3(kThreads), 0, s, g, p, m, gH, D, ms_map, lam_loc, lam, g_ms);
     return hipGetLastError();
 }
 

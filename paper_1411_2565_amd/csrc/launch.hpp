@@ -49,6 +49,13 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
                         const float *ms_map, const float *h_map, uint32_t terms, int mode,
                         float dt, int renorm, float *out_m, float *out_h, int *flag, hipStream_t s);
 
+// adjoint of one Euler step: local part (a) and the non-local completion (b)
+hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
+                        const float *h_map, const float *lam1, float dt, int renorm, float *gH, float *lam_loc,
+                        float *g_hext, float *g_ms, hipStream_t s);
+hipError_t launch_adj_b(const Geo &g, const LocalParams &p, const float *m, const float *gH, const float *D,
+                        const float *ms_map, const float *lam_loc, float *lam, float *g_ms, hipStream_t s);
+
 // FP64 reductions
 hipError_t launch_energy(const Geo &g, const EnergyParams &p, const float *m, const float *Hd,
                          const float *ms_map, const float *h_map, double *partials, double *out,

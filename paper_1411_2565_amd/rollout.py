@@ -1,0 +1,70 @@
+"""Differentiable Euler rollout with sqrt(T) checkpointing.
+
+``LLGRollout.apply(m0, hext_map, ms_map, sim, T, dt)`` advances the state T
+explicit-Euler steps of the LLG equation (Zhu, arXiv:1411.2565, eq. (3), with
+the effective field of eq. (2)) on the GPU and returns m_T.  Its backward
+pass returns dL/dm0, dL/dh_ext (per-cell map, A/m) and dL/dMs (per-cell map)
+for any loss L(m_T), using the library's hand-written adjoint step.
+
+Memory: the forward keeps one state every S = ceil(sqrt(T)) steps.  The
+backward walks the segments from last to first; for each it replays the S
+forward steps from the checkpoint while storing every state and its
+demagnetising field (mm_forward_store), then runs S adjoint steps backwards
+(mm_adjoint_step).  The replay uses the same kernels in the same order as
+the forward pass, so the recomputed states are bitwise those of the forward.
+"""
+import math
+
+import torch
+
+from . import binding as B
+
+
+def _segments(T, S):
+    return [(k, min(S, T - k)) for k in range(0, T, S)]
+
+
+class LLGRollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None):
+        T = int(T)
+        S = int(seg) if seg else max(1, math.ceil(math.sqrt(T)))
+        sim.set_hext_map(hext_map.detach().contiguous())
+        sim.set_ms_map(ms_map.detach().contiguous())
+        m = m0.detach().contiguous().clone()
+        ckpts = []
+        for (_, n) in _segments(T, S):
+            ckpts.append(m.clone())
+            sim.step(m, n, dt, flags)
+        ctx.sim, ctx.T, ctx.dt, ctx.flags, ctx.S = sim, T, dt, flags, S
+        ctx.ckpts = ckpts
+        ctx.maps = (hext_map.detach().contiguous(), ms_map.detach().contiguous())
+        return m
+
+    @staticmethod
+    def backward(ctx, grad):
+        sim, T, dt, flags, S = ctx.sim, ctx.T, ctx.dt, ctx.flags, ctx.S
+        hmap, msmap = ctx.maps
+        sim.set_hext_map(hmap)
+        sim.set_ms_map(msmap)
+        lam = grad.detach().contiguous().clone().float()
+        g_h = torch.zeros_like(hmap)
+        g_ms = torch.zeros_like(msmap)
+        N = sim.N
+        segs = _segments(T, S)
+        mtraj = torch.empty((S, 3 * N), dtype=torch.float32, device=lam.device)
+        hdtraj = torch.empty_like(mtraj)
+        for idx in range(len(segs) - 1, -1, -1):
+            _, n = segs[idx]
+            m = ctx.ckpts[idx].clone()
+            sim._s()
+            B.mm_forward_store(sim.ctx, m, n, dt, flags, mtraj[:n], hdtraj[:n], N)
+            for s in range(n - 1, -1, -1):
+                B.mm_adjoint_step(sim.ctx, mtraj[s], hdtraj[s], lam, g_h, g_ms, dt, flags, N)
+        ctx.ckpts = None
+        return lam, g_h, g_ms, None, None, None, None, None
+
+
+def rollout(m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None):
+    """m_T of a T-step Euler rollout, differentiable in m0, hext_map, ms_map."""
+    return LLGRollout.apply(m0, hext_map, ms_map, sim, T, dt, flags, seg)
