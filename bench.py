@@ -115,6 +115,51 @@ def adjoint_ratio(binding, T=2000):
             "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "ratio": round(bwd / fwd, 3)}
 
 
+def batch_rate(binding, steps=5000, single_steps=200):
+    """Aggregate cell-steps/s of the 64-film batch (grouped launches per
+    padded size, 32-step hipGraph chunks) against the same films stepped one
+    by one (eager launches), on the same GPU."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    films = workloads.batch_films(count=64, seed=0)
+    w0 = films[0][0]
+    cells = sum(w.N for (w, _, _) in films)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B = binding.Batch([w.n for (w, _, _) in films], w0.d, Ms=w0.Ms, A=w0.A, alpha=w0.alpha,
+                          hext=[tuple(h) for (_, _, h) in films])
+        m = B.pack([m0 for (_, m0, _) in films])
+        B.step(m, 64, w0.dt, binding.MM_F_GRAPH)
+        B.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.step(m, steps, w0.dt, binding.MM_F_GRAPH)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        B.sync()
+        B.close()
+        sims = []
+        states = []
+        for (w, m0, h) in films:
+            sims.append(binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=tuple(h)))
+            states.append(torch.tensor(m0, dtype=torch.float32, device="cuda:0"))
+        for sim, st in zip(sims, states):
+            sim.step(st, 4, w0.dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sim, st in zip(sims, states):
+            sim.step(st, single_steps, w0.dt)
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for sim in sims:
+            sim.close()
+    return {"workload": f"64 films, {cells} cells in all, 4x4x3 nm, dt=5e-14",
+            "batched_cell_steps_per_s": cells * steps / tb, "batched_us_per_step": round(1e6 * tb / steps, 1),
+            "one_by_one_cell_steps_per_s": cells * single_steps / ts,
+            "one_by_one_us_per_step": round(1e6 * ts / single_steps, 1),
+            "speedup": round((cells * steps / tb) / (cells * single_steps / ts), 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,6 +170,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--compensated", action="store_true", help="time the compensated spectral multiply")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -185,6 +231,11 @@ def main():
         print("bench: adjoint/forward ratio on the 128x128x4 film", file=sys.stderr, flush=True)
         adj = adjoint_ratio(binding)
 
+    bat = None
+    if not args.no_batch:
+        print("bench: batched films", file=sys.stderr, flush=True)
+        bat = batch_rate(binding)
+
     cpu = None
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
@@ -214,6 +265,7 @@ def main():
         "kernels": kernels,
         "tensor_build_s": round(t_build, 3),
         "adjoint": adj,
+        "batch": bat,
     }
     print(json.dumps(line), flush=True)
 

@@ -77,7 +77,8 @@ enum { MM_T_EXCH = 1, MM_T_DEMAG = 2, MM_T_ANIS = 4, MM_T_ZEEMAN = 8, MM_T_ALL =
 /* Step flags. */
 enum {
     MM_F_NO_RENORM = 1,    /* skip m <- m/|m| after each Euler step */
-    MM_F_COMPENSATED = 2   /* compensated (Dot2) FP32 spectral tensor multiply */
+    MM_F_COMPENSATED = 2,  /* compensated (Dot2) FP32 spectral tensor multiply */
+    MM_F_GRAPH = 4         /* mm_step_llg: replay captured chunks of 32 steps (needs a non-null stream) */
 };
 
 /* Create a context for a geometry on HIP device `device`; work is enqueued
@@ -140,7 +141,12 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m_dev, float *h_dev, uint32_t 
 /* Advance m_dev in place by nsteps explicit-Euler steps of eq. (3) with all
  * four field terms:
  *     m <- m + dt * (-gamma0/(1+alpha^2)) [m x H + alpha m x (m x H)],
- * followed by m <- m/|m| unless MM_F_NO_RENORM.  dt > 0, nsteps >= 0. */
+ * followed by m <- m/|m| unless MM_F_NO_RENORM.  dt > 0, nsteps >= 0.
+ * With MM_F_GRAPH the steps are enqueued as replays of a HIP graph holding a
+ * chunk of 32 steps (or the largest even count below nsteps), captured on
+ * the first such call for this (m_dev, dt, flags, stream) and kept until a
+ * setter changes what the kernels read; results are identical to the eager
+ * path.  The capture requires a non-null stream. */
 mm_status mm_step_llg(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32_t flags);
 
 /* FP64 reductions of the energy of eq. (1) summed over cells and of the
@@ -198,6 +204,39 @@ mm_status mm_kernel_timing(mm_ctx *c, int enable);
  * return, per MM_K_* identifier, the accumulated milliseconds (ms[MM_K_COUNT])
  * and number of launches (launches[MM_K_COUNT]); host pointers. */
 mm_status mm_kernel_times(mm_ctx *c, double *ms, int64_t *launches);
+
+/* ---- Batched samples --------------------------------------------------
+ * Many independent grids of rectangular cells (one cell size and material,
+ * each its own nx, ny, nz and uniform external field) advanced together by
+ * the same step as mm_step_llg.  Samples with equal padded sizes share one
+ * tensor spectrum and one launch per pass (up to 32 samples per launch).
+ * The state of all samples is one packed FP32 device array: sample b's
+ * [3][nz][ny][nx] block starts at float offset offsets[b]
+ * (mm_batch_state_offsets), each block 16-byte aligned. */
+typedef struct mm_batch mm_batch;
+
+/* count samples (1..65536), n = count triples (nx, ny, nz) on the host, each
+ * within the single-sample limits; cell size dx, dy, dz (m). */
+mm_status mm_batch_create(mm_batch **out, int count, const int32_t *n, double dx, double dy, double dz,
+                          int device, void *hip_stream);
+mm_status mm_batch_destroy(mm_batch *b);
+mm_status mm_batch_set_stream(mm_batch *b, void *hip_stream);
+/* Float offsets of each sample in the packed state; offsets[count] is the
+ * packed length (count + 1 int64 on the host). */
+mm_status mm_batch_state_offsets(const mm_batch *b, int64_t *offsets);
+mm_status mm_batch_workspace_size(const mm_batch *b, size_t *bytes);
+mm_status mm_batch_set_workspace(mm_batch *b, void *dev_ptr, size_t bytes);
+/* shared material (same checks as mm_set_material) */
+mm_status mm_batch_set_material(mm_batch *b, const mm_material *mat);
+/* per-sample uniform external fields: 3*count doubles on the host, A/m */
+mm_status mm_batch_set_hext(mm_batch *b, const double *h);
+/* one FP64-built spectrum per padded size; synchronous */
+mm_status mm_batch_build_tensor(mm_batch *b);
+/* nsteps Euler steps of every sample, in place in the packed state; flags
+ * as mm_step_llg (MM_F_GRAPH captures chunks of 32 steps of the whole batch) */
+mm_status mm_batch_step(mm_batch *b, float *m_packed, int64_t nsteps, double dt, uint32_t flags);
+mm_status mm_batch_sync(mm_batch *b);
+const char *mm_batch_last_error(const mm_batch *b);
 
 /* Wait for the context's stream; report a HIP error or a non-finite state
  * flagged by an earlier step (MM_ENONFINITE, flag cleared on report). */

@@ -15,7 +15,7 @@ from . import build as _build
 
 MM_OK, MM_EINVAL, MM_ESTATE, MM_ENOMEM, MM_EHIP, MM_EUNSUP, MM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MM_T_EXCH, MM_T_DEMAG, MM_T_ANIS, MM_T_ZEEMAN, MM_T_ALL = 1, 2, 4, 8, 15
-MM_F_NO_RENORM, MM_F_COMPENSATED = 1, 2
+MM_F_NO_RENORM, MM_F_COMPENSATED, MM_F_GRAPH = 1, 2, 4
 
 _NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ESTATE", -3: "MM_ENOMEM", -4: "MM_EHIP",
           -5: "MM_EUNSUP", -6: "MM_ENONFINITE"}
@@ -73,12 +73,28 @@ def load():
         "mm_adjoint_step": [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_uint32],
         "mm_kernel_times": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
     }
+    sig.update({
+        "mm_batch_create": [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_double,
+                            ctypes.c_double, ctypes.c_double, ctypes.c_int, _P],
+        "mm_batch_destroy": [_P],
+        "mm_batch_set_stream": [_P, _P],
+        "mm_batch_state_offsets": [_P, ctypes.POINTER(ctypes.c_int64)],
+        "mm_batch_workspace_size": [_P, ctypes.POINTER(ctypes.c_size_t)],
+        "mm_batch_set_workspace": [_P, _P, ctypes.c_size_t],
+        "mm_batch_set_material": [_P, ctypes.POINTER(mm_material)],
+        "mm_batch_set_hext": [_P, ctypes.POINTER(ctypes.c_double)],
+        "mm_batch_build_tensor": [_P],
+        "mm_batch_step": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32],
+        "mm_batch_sync": [_P],
+    })
     for name, args in sig.items():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = st
     L.mm_last_error.argtypes = [_P]
     L.mm_last_error.restype = ctypes.c_char_p
+    L.mm_batch_last_error.argtypes = [_P]
+    L.mm_batch_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
 
@@ -227,6 +243,127 @@ def mm_kernel_times(ctx):
     cnt = (ctypes.c_int64 * n)()
     _check(ctx, load().mm_kernel_times(ctx, ms, cnt), "mm_kernel_times")
     return {k: (ms[i], cnt[i]) for i, k in enumerate(MM_K_NAMES)}
+
+
+def _bcheck(b, status, what):
+    if status != MM_OK:
+        msg = load().mm_batch_last_error(b).decode() if b else ""
+        raise MMError(status, f"{what}: {msg}")
+
+
+def mm_batch_create(sizes, d, device=0, stream=None):
+    arr = (ctypes.c_int32 * (3 * len(sizes)))(*[int(v) for s in sizes for v in s])
+    b = _P()
+    s = stream if stream is not None else _stream()
+    _bcheck(None, load().mm_batch_create(ctypes.byref(b), len(sizes), arr, float(d[0]), float(d[1]), float(d[2]),
+                                         int(device), s), "mm_batch_create")
+    return b
+
+
+def mm_batch_destroy(b):
+    _bcheck(None, load().mm_batch_destroy(b), "mm_batch_destroy")
+
+
+def mm_batch_set_stream(b, stream=None):
+    _bcheck(b, load().mm_batch_set_stream(b, stream if stream is not None else _stream()), "mm_batch_set_stream")
+
+
+def mm_batch_state_offsets(b, count):
+    off = (ctypes.c_int64 * (count + 1))()
+    _bcheck(b, load().mm_batch_state_offsets(b, off), "mm_batch_state_offsets")
+    return list(off)
+
+
+def mm_batch_workspace_size(b):
+    v = ctypes.c_size_t()
+    _bcheck(b, load().mm_batch_workspace_size(b, ctypes.byref(v)), "mm_batch_workspace_size")
+    return v.value
+
+
+def mm_batch_set_workspace(b, ws):
+    _bcheck(b, load().mm_batch_set_workspace(b, ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size()),
+            "mm_batch_set_workspace")
+
+
+def mm_batch_set_material(b, Ms, A, Ku=0.0, u=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5):
+    m = mm_material(float(Ms), float(A), float(Ku), (ctypes.c_double * 3)(*map(float, u)), float(alpha), float(gamma0))
+    _bcheck(b, load().mm_batch_set_material(b, ctypes.byref(m)), "mm_batch_set_material")
+
+
+def mm_batch_set_hext(b, h):
+    flat = [float(v) for row in h for v in row]
+    _bcheck(b, load().mm_batch_set_hext(b, (ctypes.c_double * len(flat))(*flat)), "mm_batch_set_hext")
+
+
+def mm_batch_build_tensor(b):
+    _bcheck(b, load().mm_batch_build_tensor(b), "mm_batch_build_tensor")
+
+
+def mm_batch_step(b, m, nsteps, dt, flags, total):
+    import torch
+    _bcheck(b, load().mm_batch_step(b, _dev(m, torch.float32, total, "packed state"), int(nsteps), float(dt),
+                                    int(flags)), "mm_batch_step")
+
+
+def mm_batch_sync(b):
+    _bcheck(b, load().mm_batch_sync(b), "mm_batch_sync")
+
+
+class Batch:
+    """Many independent samples (own sizes and uniform fields, one cell size
+    and material) on one GPU; the state is one packed tensor."""
+
+    def __init__(self, sizes, d, Ms, A, Ku=0.0, u=(1.0, 0.0, 0.0), alpha=0.5, gamma0=2.211e5, hext=None, device=0):
+        import torch
+        self.sizes = [tuple(int(v) for v in s) for s in sizes]
+        self.device = torch.device("cuda", device)
+        with torch.cuda.device(self.device):
+            self.b = mm_batch_create(self.sizes, d, device)
+            self.offsets = mm_batch_state_offsets(self.b, len(self.sizes))
+            nbytes = mm_batch_workspace_size(self.b)
+            self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            off = (-self.ws.data_ptr()) % 256
+            mm_batch_set_workspace(self.b, self.ws[off:off + nbytes])
+            mm_batch_set_material(self.b, Ms, A, Ku, u, alpha, gamma0)
+            mm_batch_set_hext(self.b, hext if hext is not None else [(0.0, 0.0, 0.0)] * len(self.sizes))
+            mm_batch_build_tensor(self.b)
+
+    @property
+    def total(self):
+        return self.offsets[-1]
+
+    def pack(self, states):
+        """Packed device state from a list of [3][nz][ny][nx] arrays."""
+        import torch
+        out = torch.zeros(self.total, dtype=torch.float32, device=self.device)
+        for s, o in zip(states, self.offsets):
+            t = torch.as_tensor(s, dtype=torch.float32).reshape(-1)
+            out[o:o + t.numel()] = t.to(self.device)
+        return out
+
+    def unpack(self, packed, i):
+        nx, ny, nz = self.sizes[i]
+        o = self.offsets[i]
+        return packed[o:o + 3 * nx * ny * nz].reshape(3, nz, ny, nx)
+
+    def step(self, m, nsteps, dt, flags=0):
+        mm_batch_set_stream(self.b)
+        mm_batch_step(self.b, m, nsteps, dt, flags, self.total)
+        return m
+
+    def sync(self):
+        mm_batch_sync(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            mm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # -------------------------------------------------------------- convenience

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -54,6 +55,22 @@ struct mm_ctx {
     size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
     std::string err;
+    // captured step chunks (MM_F_GRAPH): kernel arguments (state pointer,
+    // material, fields, maps, dt) are baked in, so every setter drops them
+    struct GraphEntry {
+        const float *m;
+        int64_t n;
+        double dt;
+        uint32_t flags;
+        hipStream_t stream;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    void drop_graphs()
+    {
+        for (auto &e : graphs) (void)hipGraphExecDestroy(e.exec);
+        graphs.clear();
+    }
     // diagnostic per-kernel timing
     bool timing = false;
     std::vector<hipEvent_t> ev_free;
@@ -64,6 +81,7 @@ struct mm_ctx {
 
     ~mm_ctx()
     {
+        drop_graphs();
         for (auto &p : pending) {
             (void)hipEventDestroy(p.a);
             (void)hipEventDestroy(p.b);
@@ -337,6 +355,7 @@ mm_status mm_set_workspace(mm_ctx *c, void *dev_ptr, size_t bytes)
         return fail(c, MM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, c->total);
     c->ws = static_cast<char *>(dev_ptr);
     c->ws_bytes = bytes;
+    c->drop_graphs();
     c->tensor = false;
     c->ms_map = false;
     c->h_map = false;
@@ -358,6 +377,7 @@ mm_status mm_set_material(mm_ctx *c, const mm_material *m)
     c->mat = *m;
     for (int i = 0; i < 3; ++i) c->mat.u[i] = m->u[i] / un;
     c->have_mat = true;
+    c->drop_graphs();
     return MM_OK;
 }
 
@@ -367,6 +387,7 @@ mm_status mm_set_ms_map(mm_ctx *c, const float *ms)
     MM_TRY(need_ws(c));
     if (!ms) {
         c->ms_map = false;
+        c->drop_graphs();
         return MM_OK;
     }
     if (!aligned16(ms)) return fail(c, MM_EINVAL, "Ms map must be 16-byte aligned");
@@ -374,6 +395,7 @@ mm_status mm_set_ms_map(mm_ctx *c, const float *ms)
     MM_TRY(hipcheck(c, hipMemcpyAsync(c->at<float>(c->o_ms), ms, sizeof(float) * c->g.N, hipMemcpyDeviceToDevice,
                                       c->stream), "copy Ms map"));
     c->ms_map = true;
+    c->drop_graphs();
     return MM_OK;
 }
 
@@ -384,6 +406,7 @@ mm_status mm_set_hext(mm_ctx *c, const double h[3])
     for (int i = 0; i < 3; ++i)
         if (!std::isfinite(h[i])) return fail(c, MM_EINVAL, "field must be finite");
     for (int i = 0; i < 3; ++i) c->hext[i] = h[i];
+    c->drop_graphs();
     return MM_OK;
 }
 
@@ -393,6 +416,7 @@ mm_status mm_set_hext_map(mm_ctx *c, const float *h)
     MM_TRY(need_ws(c));
     if (!h) {
         c->h_map = false;
+        c->drop_graphs();
         return MM_OK;
     }
     if (!aligned16(h)) return fail(c, MM_EINVAL, "field map must be 16-byte aligned");
@@ -400,6 +424,7 @@ mm_status mm_set_hext_map(mm_ctx *c, const float *h)
     MM_TRY(hipcheck(c, hipMemcpyAsync(c->at<float>(c->o_h), h, sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice,
                                       c->stream), "copy field map"));
     c->h_map = true;
+    c->drop_graphs();
     return MM_OK;
 }
 
@@ -446,11 +471,13 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m, float *h, uint32_t terms)
     });
 }
 
-mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
+}  // extern "C"
+
+namespace {
+
+// enqueue nsteps Euler steps on the context's stream (no checks)
+mm_status enqueue_steps(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
 {
-    if (!c) return MM_EINVAL;
-    MM_TRY(check_step_args(c, m, nsteps, dt, flags));
-    MM_TRY(set_device(c));
     const mmk::LocalParams p = local_params(c);
     const bool comp = flags & MM_F_COMPENSATED;
     const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
@@ -472,10 +499,65 @@ mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t f
     return MM_OK;
 }
 
+// captured chunk of n (even) steps for this state pointer, dt and flags
+mm_status graph_for(mm_ctx *c, float *m, int64_t n, double dt, uint32_t flags, hipGraphExec_t *out)
+{
+    for (auto &e : c->graphs)
+        if (e.m == m && e.n == n && e.dt == dt && e.flags == flags && e.stream == c->stream) {
+            *out = e.exec;
+            return MM_OK;
+        }
+    const bool was_timing = c->timing;
+    c->timing = false;
+    MM_TRY(hipcheck(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture"));
+    mm_status st = enqueue_steps(c, m, n, dt, flags);
+    hipGraph_t graph = nullptr;
+    const hipError_t e_end = hipStreamEndCapture(c->stream, &graph);
+    c->timing = was_timing;
+    if (st != MM_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    MM_TRY(hipcheck(c, e_end, "end capture"));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    MM_TRY(hipcheck(c, e_inst, "instantiate graph"));
+    c->graphs.push_back({m, n, dt, flags, c->stream, exec});
+    *out = exec;
+    return MM_OK;
+}
+
+constexpr int64_t kGraphChunk = 32;  // steps per captured graph
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
+{
+    if (!c) return MM_EINVAL;
+    const uint32_t step_flags = flags & ~uint32_t(MM_F_GRAPH);
+    MM_TRY(check_step_args(c, m, nsteps, dt, step_flags));
+    MM_TRY(set_device(c));
+    if (!(flags & MM_F_GRAPH)) return enqueue_steps(c, m, nsteps, dt, step_flags);
+    if (!c->stream) return fail(c, MM_EINVAL, "MM_F_GRAPH needs a non-null stream (capture is not allowed on it)");
+    int64_t chunk = nsteps >= kGraphChunk ? kGraphChunk : (nsteps & ~int64_t(1));
+    int64_t done = 0;
+    if (chunk >= 2) {
+        hipGraphExec_t exec = nullptr;
+        MM_TRY(graph_for(c, m, chunk, dt, step_flags, &exec));
+        for (; done + chunk <= nsteps; done += chunk)
+            MM_TRY(hipcheck(c, hipGraphLaunch(exec, c->stream), "graph launch"));
+    }
+    return enqueue_steps(c, m, nsteps - done, dt, step_flags);
+}
+
 mm_status mm_set_compensated(mm_ctx *c, int on)
 {
     if (!c) return MM_EINVAL;
     c->compensated = on != 0;
+    c->drop_graphs();
     return MM_OK;
 }
 
@@ -612,6 +694,407 @@ const char *mm_last_error(const mm_ctx *c)
 {
     if (!c) return "null context";
     return c->err.c_str();
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Batched samples: many independent grids (each its own nx, ny, nz and
+// external field, one cell size and material) advanced together.  Samples
+// with the same padded size form a group; every pass runs as one launch per
+// group of up to kMaxBatch samples.  The tensor spectrum depends only on the
+// padded size and the cell size, so each group shares one spectrum, built as
+// for an (Px/2, Py/2, Pz/2) grid: a sample with n <= P/2 never reaches the
+// offsets beyond its own extent in the zero-padded convolution.
+// ===========================================================================
+
+struct mm_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double d[3] = {0, 0, 0};
+    mm_material mat{};
+    bool have_mat = false, tensor = false;
+    struct Sample {
+        mmk::Geo g;
+        size_t m_off = 0;                  // offset in the packed state (floats)
+        size_t o_S1 = 0, o_S2 = 0, o_mt = 0;  // workspace byte offsets
+        int group = 0;
+        double h[3] = {0, 0, 0};
+    };
+    struct Group {
+        mmk::Geo g;          // padded sizes of the group (n = P/2)
+        size_t o_K = 0;      // its tensor spectrum
+        std::vector<int> members;
+    };
+    std::vector<Sample> samples;
+    std::vector<Group> groups;
+    size_t total_state = 0;  // floats in the packed state
+    size_t o_flag = 0, total = 0;
+    char *ws = nullptr;
+    std::string err;
+    std::vector<hipGraphExec_t> graph_exec;
+    std::vector<std::pair<const float *, std::pair<int64_t, double>>> graph_key;
+    std::vector<uint32_t> graph_flags;
+    void drop_graphs()
+    {
+        for (auto e : graph_exec) (void)hipGraphExecDestroy(e);
+        graph_exec.clear();
+        graph_key.clear();
+        graph_flags.clear();
+    }
+    ~mm_batch() { drop_graphs(); }
+    template <typename T>
+    T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+mm_status bfail(mm_batch *b, mm_status s, const char *fmt, ...)
+{
+    if (b) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        b->err = buf;
+    }
+    return s;
+}
+
+mm_status bhip(mm_batch *b, hipError_t e, const char *what)
+{
+    if (e != hipSuccess) return bfail(b, MM_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return MM_OK;
+}
+
+mmk::Geo make_geo(int nx, int ny, int nz, int Px, int Py, int Pz)
+{
+    mmk::Geo g{};
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.Px = Px;
+    g.Py = Py;
+    g.Pz = Pz;
+    g.Hx = Px / 2 + 1;
+    g.Hy = Py == 1 ? 1 : Py / 2 + 1;
+    g.Hz = Pz == 1 ? 1 : Pz / 2 + 1;
+    g.N = (long long)nx * ny * nz;
+    return g;
+}
+
+mmk::LocalParams batch_params(const mm_batch *b)
+{
+    mmk::LocalParams p{};
+    const mm_material &m = b->mat;
+    p.ms = (float)m.Ms;
+    p.ax = (float)(2.0 * m.A / (kMu0 * b->d[0] * b->d[0]));
+    p.ay = (float)(2.0 * m.A / (kMu0 * b->d[1] * b->d[1]));
+    p.az = (float)(2.0 * m.A / (kMu0 * b->d[2] * b->d[2]));
+    p.ku2 = (float)(2.0 * m.Ku / kMu0);
+    p.u0 = (float)m.u[0];
+    p.u1 = (float)m.u[1];
+    p.u2 = (float)m.u[2];
+    const double c1 = -m.gamma0 / (1.0 + m.alpha * m.alpha);
+    p.c1 = (float)c1;
+    p.c2 = (float)(m.alpha * c1);
+    return p;
+}
+
+// enqueue nsteps steps of every sample (no checks)
+mm_status batch_enqueue(mm_batch *b, float *m, int64_t nsteps, double dt, uint32_t flags)
+{
+    const mmk::LocalParams p = batch_params(b);
+    const bool comp = flags & MM_F_COMPENSATED;
+    const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
+    int *flag = b->at<int>(b->o_flag);
+    hipStream_t st = b->stream;
+    std::vector<mmk::XfwdDesc> xf;
+    std::vector<mmk::YDesc> yf, yi;
+    std::vector<mmk::ZDesc> zc;
+    std::vector<mmk::XinvDesc> xi;
+    std::vector<mmk::LocalDesc> lc;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        for (const auto &gr : b->groups) {
+            for (size_t k0 = 0; k0 < gr.members.size(); k0 += mmk::kMaxBatch) {
+                const int cnt = (int)std::min<size_t>(mmk::kMaxBatch, gr.members.size() - k0);
+                xf.clear(); yf.clear(); yi.clear(); zc.clear(); xi.clear(); lc.clear();
+                for (int k = 0; k < cnt; ++k) {
+                    const auto &sm = b->samples[gr.members[k0 + k]];
+                    float *mb[2] = {m + sm.m_off, b->at<float>(sm.o_mt)};
+                    const float *src = mb[s & 1];
+                    float *dst = mb[(s + 1) & 1];
+                    float2 *S1 = b->at<float2>(sm.o_S1), *S2 = b->at<float2>(sm.o_S2);
+                    float *Hd = b->at<float>(sm.o_S2);
+                    xf.push_back({sm.g, src, nullptr, S1, (float)b->mat.Ms});
+                    yf.push_back({sm.g, S1, S2});
+                    zc.push_back({sm.g, S2, b->at<float>(gr.o_K)});
+                    yi.push_back({sm.g, S2, S1});
+                    xi.push_back({sm.g, S1, Hd});
+                    lc.push_back({sm.g, src, Hd, nullptr, nullptr, dst, nullptr, (float)sm.h[0], (float)sm.h[1],
+                                  (float)sm.h[2]});
+                }
+                MM_TRY(bhip(b, mmk::launch_xfwd(xf.data(), cnt, st), "batch xfwd"));
+                MM_TRY(bhip(b, mmk::launch_yfwd(yf.data(), cnt, st), "batch yfwd"));
+                MM_TRY(bhip(b, mmk::launch_zconv(zc.data(), cnt, comp, st), "batch zconv"));
+                MM_TRY(bhip(b, mmk::launch_yinv(yi.data(), cnt, st), "batch yinv"));
+                MM_TRY(bhip(b, mmk::launch_xinv(xi.data(), cnt, st), "batch xinv"));
+                MM_TRY(bhip(b, mmk::launch_local_batch(lc.data(), cnt, p, MM_T_ALL, 1, (float)dt, renorm, flag, st),
+                            "batch local"));
+            }
+        }
+    }
+    if (nsteps & 1)
+        for (const auto &sm : b->samples)
+            MM_TRY(bhip(b, hipMemcpyAsync(m + sm.m_off, b->at<float>(sm.o_mt), sizeof(float) * 3 * sm.g.N,
+                                          hipMemcpyDeviceToDevice, st),
+                        "copy back state"));
+    return MM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mm_status mm_batch_create(mm_batch **out, int count, const int32_t *n, double dx, double dy, double dz, int device,
+                          void *hip_stream)
+{
+    if (!out || !n || count < 1 || count > 65536) return MM_EINVAL;
+    *out = nullptr;
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
+        return MM_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        const int nx = n[3 * i], ny = n[3 * i + 1], nz = n[3 * i + 2];
+        if (nx < 2 || nx > kMaxN || ny < 1 || ny > kMaxN || nz < 1 || nz > kMaxN) return MM_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return MM_EINVAL;
+    mm_batch *b = new (std::nothrow) mm_batch();
+    if (!b) return MM_ENOMEM;
+    b->device = device;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->d[0] = dx;
+    b->d[1] = dy;
+    b->d[2] = dz;
+    b->samples.resize(count);
+    size_t moff = 0;
+    for (int i = 0; i < count; ++i) {
+        auto &sm = b->samples[i];
+        const int nx = n[3 * i], ny = n[3 * i + 1], nz = n[3 * i + 2];
+        sm.g = make_geo(nx, ny, nz, padded(nx), padded(ny), padded(nz));
+        sm.m_off = moff;
+        moff += (3 * (size_t)sm.g.N + 3) & ~size_t(3);  // 16-byte aligned sample slots
+        int gi = -1;
+        for (size_t k = 0; k < b->groups.size(); ++k)
+            if (b->groups[k].g.Px == sm.g.Px && b->groups[k].g.Py == sm.g.Py && b->groups[k].g.Pz == sm.g.Pz)
+                gi = (int)k;
+        if (gi < 0) {
+            mm_batch::Group gr;
+            gr.g = make_geo(sm.g.Px / 2, sm.g.Py > 1 ? sm.g.Py / 2 : 1, sm.g.Pz > 1 ? sm.g.Pz / 2 : 1, sm.g.Px,
+                            sm.g.Py, sm.g.Pz);
+            b->groups.push_back(gr);
+            gi = (int)b->groups.size() - 1;
+        }
+        sm.group = gi;
+        b->groups[gi].members.push_back(i);
+    }
+    b->total_state = moff;
+    // workspace: spectra, flag, then per-sample buffers aliased with the
+    // tensor-build temporaries of the largest group
+    Carve cv;
+    for (auto &gr : b->groups) gr.o_K = cv.take(sizeof(float) * 6 * (size_t)gr.g.Hx * gr.g.Hy * gr.g.Hz);
+    b->o_flag = cv.take(256);
+    const size_t region = cv.off;
+    Carve st;
+    st.off = region;
+    for (auto &sm : b->samples) {
+        sm.o_S1 = st.take(sizeof(float2) * 3 * (size_t)sm.g.nz * sm.g.Hx * sm.g.ny);
+        sm.o_S2 = st.take(sizeof(float2) * 3 * (size_t)sm.g.nz * sm.g.Hx * sm.g.Py);
+        sm.o_mt = st.take(sizeof(float) * 3 * (size_t)sm.g.N);
+    }
+    size_t tmax = 0;
+    for (auto &gr : b->groups) {
+        const mmk::Geo &g = gr.g;
+        Carve tb;
+        tb.take(sizeof(double) * 6 * (size_t)g.N);
+        const size_t a1 = (size_t)g.nz * g.ny * g.Hx, a2 = (size_t)g.Hz * g.Hy * g.Hx;
+        tb.take(sizeof(double) * (a1 > a2 ? a1 : a2));
+        tb.take(sizeof(double) * (size_t)g.nz * g.Hy * g.Hx);
+        tmax = tb.off > tmax ? tb.off : tmax;
+    }
+    b->total = std::max(st.off, region + tmax);
+    if (hipSetDevice(device) != hipSuccess) {
+        delete b;
+        return MM_EHIP;
+    }
+    {
+        mm_ctx tmp;
+        tmp.device = device;
+        tmp.stream = b->stream;
+        if (init_device(&tmp) != MM_OK) {
+            delete b;
+            return MM_EHIP;
+        }
+    }
+    *out = b;
+    return MM_OK;
+}
+
+mm_status mm_batch_destroy(mm_batch *b)
+{
+    if (!b) return MM_EINVAL;
+    delete b;
+    return MM_OK;
+}
+
+mm_status mm_batch_set_stream(mm_batch *b, void *hip_stream)
+{
+    if (!b) return MM_EINVAL;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    return MM_OK;
+}
+
+mm_status mm_batch_workspace_size(const mm_batch *b, size_t *bytes)
+{
+    if (!b || !bytes) return MM_EINVAL;
+    *bytes = b->total;
+    return MM_OK;
+}
+
+mm_status mm_batch_state_offsets(const mm_batch *b, int64_t *offsets)
+{
+    if (!b || !offsets) return MM_EINVAL;
+    for (size_t i = 0; i < b->samples.size(); ++i) offsets[i] = (int64_t)b->samples[i].m_off;
+    offsets[b->samples.size()] = (int64_t)b->total_state;
+    return MM_OK;
+}
+
+mm_status mm_batch_set_workspace(mm_batch *b, void *dev_ptr, size_t bytes)
+{
+    if (!b) return MM_EINVAL;
+    if (!dev_ptr) return bfail(b, MM_EINVAL, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) return bfail(b, MM_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < b->total)
+        return bfail(b, MM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, b->total);
+    b->ws = static_cast<char *>(dev_ptr);
+    b->tensor = false;
+    b->drop_graphs();
+    MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
+    return bhip(b, hipMemsetAsync(b->at<int>(b->o_flag), 0, sizeof(int), b->stream), "clear flag");
+}
+
+mm_status mm_batch_set_material(mm_batch *b, const mm_material *m)
+{
+    if (!b) return MM_EINVAL;
+    mm_ctx tmp;
+    const mm_status s = mm_set_material(&tmp, m);
+    if (s != MM_OK) return bfail(b, s, "%s", tmp.err.c_str());
+    b->mat = tmp.mat;
+    b->have_mat = true;
+    b->drop_graphs();
+    return MM_OK;
+}
+
+mm_status mm_batch_set_hext(mm_batch *b, const double *h)
+{
+    if (!b) return MM_EINVAL;
+    if (!h) return bfail(b, MM_EINVAL, "fields are NULL");
+    for (size_t i = 0; i < 3 * b->samples.size(); ++i)
+        if (!std::isfinite(h[i])) return bfail(b, MM_EINVAL, "fields must be finite");
+    for (size_t i = 0; i < b->samples.size(); ++i)
+        for (int k = 0; k < 3; ++k) b->samples[i].h[k] = h[3 * i + k];
+    b->drop_graphs();
+    return MM_OK;
+}
+
+mm_status mm_batch_build_tensor(mm_batch *b)
+{
+    if (!b) return MM_EINVAL;
+    if (!b->ws) return bfail(b, MM_ESTATE, "no workspace set");
+    MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
+    const size_t region = b->o_flag + 256;
+    for (auto &gr : b->groups) {
+        const mmk::Geo &g = gr.g;
+        Carve tb;
+        tb.off = region;
+        double *T = b->at<double>(tb.take(sizeof(double) * 6 * (size_t)g.N));
+        const size_t a1 = (size_t)g.nz * g.ny * g.Hx, a2 = (size_t)g.Hz * g.Hy * g.Hx;
+        double *tA = b->at<double>(tb.take(sizeof(double) * (a1 > a2 ? a1 : a2)));
+        double *tB = b->at<double>(tb.take(sizeof(double) * (size_t)g.nz * g.Hy * g.Hx));
+        MM_TRY(bhip(b, mmk::launch_tensor_octant(g, b->d[0], b->d[1], b->d[2], T, b->stream), "tensor octant"));
+        MM_TRY(bhip(b, mmk::launch_tensor_spectrum(g, T, tA, tB, b->at<float>(gr.o_K), b->stream), "tensor spectrum"));
+    }
+    MM_TRY(bhip(b, hipStreamSynchronize(b->stream), "tensor build sync"));
+    b->tensor = true;
+    return MM_OK;
+}
+
+mm_status mm_batch_step(mm_batch *b, float *m, int64_t nsteps, double dt, uint32_t flags)
+{
+    if (!b) return MM_EINVAL;
+    if (!m || !aligned16(m)) return bfail(b, MM_EINVAL, "m must be a 16-byte aligned device pointer");
+    if (nsteps < 0) return bfail(b, MM_EINVAL, "nsteps must be >= 0");
+    if (!(dt > 0) || !std::isfinite(dt)) return bfail(b, MM_EINVAL, "dt must be finite and > 0");
+    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_GRAPH))
+        return bfail(b, MM_EINVAL, "unknown flag bits 0x%x", flags);
+    if (!b->ws) return bfail(b, MM_ESTATE, "no workspace set");
+    if (!b->have_mat) return bfail(b, MM_ESTATE, "material not set");
+    if (!b->tensor) return bfail(b, MM_ESTATE, "mm_batch_build_tensor has not been called");
+    MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
+    const uint32_t sf = flags & ~uint32_t(MM_F_GRAPH);
+    if (!(flags & MM_F_GRAPH)) return batch_enqueue(b, m, nsteps, dt, sf);
+    if (!b->stream) return bfail(b, MM_EINVAL, "MM_F_GRAPH needs a non-null stream");
+    const int64_t chunk = nsteps >= kGraphChunk ? kGraphChunk : (nsteps & ~int64_t(1));
+    int64_t done = 0;
+    if (chunk >= 2) {
+        hipGraphExec_t exec = nullptr;
+        for (size_t k = 0; k < b->graph_exec.size(); ++k)
+            if (b->graph_key[k].first == m && b->graph_key[k].second.first == chunk &&
+                b->graph_key[k].second.second == dt && b->graph_flags[k] == sf)
+                exec = b->graph_exec[k];
+        if (!exec) {
+            MM_TRY(bhip(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture"));
+            const mm_status s = batch_enqueue(b, m, chunk, dt, sf);
+            hipGraph_t graph = nullptr;
+            const hipError_t e_end = hipStreamEndCapture(b->stream, &graph);
+            if (s != MM_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return s;
+            }
+            MM_TRY(bhip(b, e_end, "end capture"));
+            const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            MM_TRY(bhip(b, e_inst, "instantiate graph"));
+            b->graph_exec.push_back(exec);
+            b->graph_key.push_back({m, {chunk, dt}});
+            b->graph_flags.push_back(sf);
+        }
+        for (; done + chunk <= nsteps; done += chunk) MM_TRY(bhip(b, hipGraphLaunch(exec, b->stream), "graph launch"));
+    }
+    return batch_enqueue(b, m, nsteps - done, dt, sf);
+}
+
+mm_status mm_batch_sync(mm_batch *b)
+{
+    if (!b) return MM_EINVAL;
+    MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
+    MM_TRY(bhip(b, hipStreamSynchronize(b->stream), "stream sync"));
+    if (b->ws) {
+        int flag = 0;
+        MM_TRY(bhip(b, hipMemcpy(&flag, b->at<int>(b->o_flag), sizeof(int), hipMemcpyDeviceToHost), "read flag"));
+        if (flag) {
+            MM_TRY(bhip(b, hipMemset(b->at<int>(b->o_flag), 0, sizeof(int)), "clear flag"));
+            return bfail(b, MM_ENONFINITE, "a step produced a non-finite magnetisation");
+        }
+    }
+    return MM_OK;
+}
+
+const char *mm_batch_last_error(const mm_batch *b)
+{
+    if (!b) return "null batch";
+    return b->err.c_str();
 }
 
 }  // extern "C"

@@ -100,16 +100,21 @@ struct XShape {
 // E[k] = (Z[k] + conj Z[L-k])/2, O[k] = (Z[k] - conj Z[L-k])/(2i).
 // The half spectrum kx in [0, L] is written transposed, S1[c][z][kx][y].
 // ------------------------------------------------------------------------
-template <int L>
-__global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Geo g, const float *__restrict__ m,
-                                                             const float *__restrict__ ms_map, float ms,
-                                                             float2 *__restrict__ S1)
+template <int L, int NB>
+__global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Batch<XfwdDesc, NB> B)
 {
     using S = XShape<L>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
+    const XfwdDesc &D = B.s[blockIdx.z];
+    const Geo &g = D.g;
+    const float *__restrict__ m = D.m;
+    const float *__restrict__ ms_map = D.ms_map;
+    const float ms = D.ms;
+    float2 *__restrict__ S1 = D.S1;
+    const int c = blockIdx.y % 3, z = blockIdx.y / 3, y0 = blockIdx.x * LPB;
+    if (z >= g.nz || y0 >= g.ny) return;
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
-    const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * LPB;
     const int y = y0 + ll;
     const bool ok = y < g.ny;
     const long long cell0 = ((long long)z * g.ny + y) * g.nx;
@@ -161,13 +166,17 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Geo g, const float 
 // a2 / a4: FFT along y of contiguous columns (length Py, ny non-zeros in /
 // ny kept out), one column per T threads.
 // ------------------------------------------------------------------------
-template <int L>
-__global__ __launch_bounds__(kThreads) void k_yfwd(Geo g, const float2 *__restrict__ S1,
-                                                   float2 *__restrict__ S2)
+template <int L, int NB>
+__global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
 {
     using S = YShape<L>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB;
     extern __shared__ float2 sm[];
+    const YDesc &D = B.s[blockIdx.z];
+    const Geo &g = D.g;
+    const float2 *__restrict__ S1 = D.in;
+    float2 *__restrict__ S2 = D.out;
+    if ((long long)blockIdx.x * LPB >= 3LL * g.nz * g.Hx) return;
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
     const long long line = (long long)blockIdx.x * LPB + ll;
     const bool ok = line < 3LL * g.nz * g.Hx;
@@ -187,13 +196,17 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(Geo g, const float2 *__restri
     }
 }
 
-template <int L>
-__global__ __launch_bounds__(kThreads) void k_yinv(Geo g, const float2 *__restrict__ S2,
-                                                   float2 *__restrict__ S1)
+template <int L, int NB>
+__global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
 {
     using S = YShape<L>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB;
     extern __shared__ float2 sm[];
+    const YDesc &D = B.s[blockIdx.z];
+    const Geo &g = D.g;
+    const float2 *__restrict__ S2 = D.in;
+    float2 *__restrict__ S1 = D.out;
+    if ((long long)blockIdx.x * LPB >= 3LL * g.nz * g.Hx) return;
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
     const long long line = (long long)blockIdx.x * LPB + ll;
     const bool ok = line < 3LL * g.nz * g.Hx;
@@ -246,13 +259,16 @@ __device__ __forceinline__ float dot3_comp(float k0, float x0, float k1, float x
     return q + s;
 }
 
-template <int L, bool COMP>
-__global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Geo g, float2 *__restrict__ S2,
-                                                              const float *__restrict__ K)
+template <int L, bool COMP, int NB>
+__global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B)
 {
     using S = ZShape<L>;
     constexpr int E = S::E, T = S::T, CB = S::CB;
     extern __shared__ float2 sm[];
+    const ZDesc &D = B.s[blockIdx.z];
+    const Geo &g = D.g;
+    float2 *__restrict__ S2 = D.S2;
+    const float *__restrict__ K = D.K;
     const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
     const int kx = blockIdx.y, ky = blockIdx.x * CB + col;
     const bool ok = ky < g.Py;
@@ -317,14 +333,18 @@ __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Geo g, float2 *__r
 // exp(+2 pi i k/Px); the unnormalised inverse length-L FFT of Z' is
 // x[2n] + i x[2n+1].
 // ------------------------------------------------------------------------
-template <int L>
-__global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Geo g, const float2 *__restrict__ S1,
-                                                             float *__restrict__ Hd)
+template <int L, int NB>
+__global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Batch<XinvDesc, NB> B)
 {
     using S = XShape<L>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
-    const int c = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * LPB;
+    const XinvDesc &D = B.s[blockIdx.z];
+    const Geo &g = D.g;
+    const float2 *__restrict__ S1 = D.S1;
+    float *__restrict__ Hd = D.Hd;
+    const int c = blockIdx.y % 3, z = blockIdx.y / 3, y0 = blockIdx.x * LPB;
+    if (z >= g.nz || y0 >= g.ny) return;
     const int nl = min(LPB, g.ny - y0);
     const float2 *in = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
     for (int idx = threadIdx.x; idx < (L + 1) * LPB; idx += S::THREADS) {
@@ -405,14 +425,18 @@ __device__ __forceinline__ void vstore(float *p, const float (&o)[V])
     }
 }
 
-template <int MODE, int V>
-__global__ __launch_bounds__(kThreads) void k_local(Geo g, LocalParams p, const float *__restrict__ m,
-                                                    const float *__restrict__ Hd,
-                                                    const float *__restrict__ ms_map,
-                                                    const float *__restrict__ h_map, uint32_t terms,
-                                                    float dt, int renorm, float *__restrict__ out_m,
-                                                    float *__restrict__ out_h, int *__restrict__ flag)
+template <int MODE, int V, int NB>
+__global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, LocalParams p, uint32_t terms,
+                                                    float dt, int renorm, int *__restrict__ flag)
 {
+    const LocalDesc &D = B.s[blockIdx.z];
+    const Geo &g = D.g;
+    const float *__restrict__ m = D.m;
+    const float *__restrict__ Hd = D.Hd;
+    const float *__restrict__ ms_map = D.ms_map;
+    const float *__restrict__ h_map = D.h_map;
+    float *__restrict__ out_m = D.m_out;
+    float *__restrict__ out_h = D.h_out;
     const long long i0 = ((long long)blockIdx.x * kThreads + threadIdx.x) * V;
     if (i0 >= g.N) return;
     const long long N = g.N;
@@ -502,9 +526,9 @@ __global__ __launch_bounds__(kThreads) void k_local(Geo g, LocalParams p, const 
         } else {
 #pragma unroll
             for (int j = 0; j < V; ++j) {
-                h[0][j] += p.h0;
-                h[1][j] += p.h1;
-                h[2][j] += p.h2;
+                h[0][j] += D.h0;
+                h[1][j] += D.h1;
+                h[2][j] += D.h2;
             }
         }
     }
@@ -969,18 +993,59 @@ __global__ __launch_bounds__(kThreads) void k_pack(Geo g, const double *__restri
 
 #define MM_LEN_CASES(X) X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
-hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s)
+template <typename Dsc, int NB>
+static Batch<Dsc, NB> pack(const Dsc *d, int count)
 {
-    switch (g.Px / 2) {
-#define CASE(LL)                                                                                  \
-    case LL: {                                                                                    \
-        if constexpr (LL <= 512) {                                                                \
-            using S = XShape<LL>;                                                                 \
-            dim3 grid((g.ny + S::LPB - 1) / S::LPB, g.nz, 3);                                     \
-            hipLaunchKernelGGL(k_xfwd<LL>, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, g, m, \
-                               ms_map, ms, S1);                                                   \
-        }                                                                                         \
-        break;                                                                                    \
+    Batch<Dsc, NB> b{};
+    for (int i = 0; i < count && i < NB; ++i) b.s[i] = d[i];
+    return b;
+}
+
+// grid extents over a batch of samples with a common padded size
+struct Extent {
+    int ny = 0, nz = 0;
+    long long lines = 0, items = 0;
+};
+template <typename Dsc>
+static Extent extent(const Dsc *d, int count)
+{
+    Extent e;
+    for (int i = 0; i < count; ++i) {
+        const Geo &g = d[i].g;
+        e.ny = g.ny > e.ny ? g.ny : e.ny;
+        e.nz = g.nz > e.nz ? g.nz : e.nz;
+        const long long l = 3LL * g.nz * g.Hx;
+        e.lines = l > e.lines ? l : e.lines;
+        const long long it = (g.nx % 4 == 0) ? g.N / 4 : g.N;
+        e.items = it > e.items ? it : e.items;
+    }
+    return e;
+}
+
+// one launch for 1 sample or up to kMaxBatch samples
+#define MM_BATCH_LAUNCH(KERNEL, DESC, GRID, BLOCK, LDS, STREAM, ...)                           \
+    do {                                                                                    \
+        if (count == 1)                                                                     \
+            hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 1>), GRID, BLOCK, LDS, STREAM,          \
+                               pack<DESC, 1>(d, count));                                    \
+        else                                                                                \
+            hipLaunchKernelGGL((KERNEL<__VA_ARGS__, kMaxBatch>), GRID, BLOCK, LDS, STREAM,  \
+                               pack<DESC, kMaxBatch>(d, count));                            \
+    } while (0)
+
+hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s)
+{
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    const Extent e = extent(d, count);
+    switch (d[0].g.Px / 2) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        if constexpr (LL <= 512) {                                                            \
+            using S = XShape<LL>;                                                             \
+            dim3 grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);                         \
+            MM_BATCH_LAUNCH(k_xfwd, XfwdDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, LL); \
+        }                                                                                     \
+        break;                                                                                \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -990,17 +1055,19 @@ hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float 
     return hipGetLastError();
 }
 
-hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
+hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s)
 {
-    switch (g.Px / 2) {
-#define CASE(LL)                                                                                  \
-    case LL: {                                                                                    \
-        if constexpr (LL <= 512) {                                                                \
-            using S = XShape<LL>;                                                                 \
-            dim3 grid((g.ny + S::LPB - 1) / S::LPB, g.nz, 3);                                     \
-            hipLaunchKernelGGL(k_xinv<LL>, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, g, S1, Hd); \
-        }                                                                                         \
-        break;                                                                                    \
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    const Extent e = extent(d, count);
+    switch (d[0].g.Px / 2) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        if constexpr (LL <= 512) {                                                            \
+            using S = XShape<LL>;                                                             \
+            dim3 grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);                         \
+            MM_BATCH_LAUNCH(k_xinv, XinvDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, LL); \
+        }                                                                                     \
+        break;                                                                                \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -1010,16 +1077,20 @@ hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s)
+static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t s)
 {
-    const long long lines = 3LL * g.nz * g.Hx;
-    switch (g.Py) {
-#define CASE(LL)                                                                                  \
-    case LL: {                                                                                    \
-        using S = YShape<LL>;                                                                     \
-        dim3 grid((unsigned)((lines + S::LPB - 1) / S::LPB));                                    \
-        hipLaunchKernelGGL(k_yfwd<LL>, grid, dim3(kThreads), S::LDS * sizeof(float2), s, g, S1, S2); \
-        break;                                                                                    \
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    const Extent e = extent(d, count);
+    switch (d[0].g.Py) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        using S = YShape<LL>;                                                                 \
+        dim3 grid((unsigned)((e.lines + S::LPB - 1) / S::LPB), 1, count);                    \
+        if (inverse)                                                                          \
+            MM_BATCH_LAUNCH(k_yinv, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, LL); \
+        else                                                                                  \
+            MM_BATCH_LAUNCH(k_yfwd, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, LL); \
+        break;                                                                                \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -1029,38 +1100,24 @@ hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s)
-{
-    const long long lines = 3LL * g.nz * g.Hx;
-    switch (g.Py) {
-#define CASE(LL)                                                                                  \
-    case LL: {                                                                                    \
-        using S = YShape<LL>;                                                                     \
-        dim3 grid((unsigned)((lines + S::LPB - 1) / S::LPB));                                    \
-        hipLaunchKernelGGL(k_yinv<LL>, grid, dim3(kThreads), S::LDS * sizeof(float2), s, g, S2, S1); \
-        break;                                                                                    \
-    }
-        MM_LEN_CASES(CASE)
-#undef CASE
-    default:
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
+hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s) { return launch_y(d, count, false, s); }
+hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s) { return launch_y(d, count, true, s); }
 
-hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s)
+hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s)
 {
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    const Geo &g = d[0].g;
     switch (g.Pz) {
-#define CASE(LL)                                                                                  \
-    case LL: {                                                                                    \
-        using S = ZShape<LL>;                                                                     \
-        dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, 1);                                           \
-        const size_t lds = S::LDS * sizeof(float2);                                               \
-        if (comp)                                                                                 \
-            hipLaunchKernelGGL((k_zconv<LL, true>), grid, dim3(S::THREADS), lds, s, g, S2, K);    \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_zconv<LL, false>), grid, dim3(S::THREADS), lds, s, g, S2, K);   \
-        break;                                                                                    \
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        using S = ZShape<LL>;                                                                 \
+        dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, count);                                   \
+        const size_t lds = S::LDS * sizeof(float2);                                           \
+        if (comp)                                                                             \
+            MM_BATCH_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, LL, true);        \
+        else                                                                                  \
+            MM_BATCH_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, LL, false);       \
+        break;                                                                                \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
@@ -1070,16 +1127,27 @@ hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hip
     return hipGetLastError();
 }
 
-hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
-                        const float *ms_map, const float *h_map, uint32_t terms, int mode, float dt,
-                        int renorm, float *out_m, float *out_h, int *flag, hipStream_t s)
+hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &p, uint32_t terms, int mode,
+                              float dt, int renorm, int *flag, hipStream_t s)
 {
-    const bool vec = (g.nx % 4) == 0;
-    const long long items = vec ? g.N / 4 : g.N;
-    dim3 grid((unsigned)((items + kThreads - 1) / kThreads));
-#define LOCAL(MODE, V)                                                                            \
-    hipLaunchKernelGGL((k_local<MODE, V>), grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, terms, dt, \
-                       renorm, out_m, out_h, flag)
+    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    bool vec = true;
+    for (int i = 0; i < count; ++i) vec = vec && (d[i].g.nx % 4 == 0);
+    long long items = 0;
+    for (int i = 0; i < count; ++i) {
+        const long long it = vec ? d[i].g.N / 4 : d[i].g.N;
+        items = it > items ? it : items;
+    }
+    dim3 grid((unsigned)((items + kThreads - 1) / kThreads), 1, count);
+#define LOCAL(MODE, V)                                                                        \
+    do {                                                                                      \
+        if (count == 1)                                                                       \
+            hipLaunchKernelGGL((k_local<MODE, V, 1>), grid, dim3(kThreads), 0, s,             \
+                               pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);     \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_local<MODE, V, kMaxBatch>), grid, dim3(kThreads), 0, s,     \
+                               pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
+    } while (0)
     if (mode == 0) {
         if (vec) LOCAL(0, 4); else LOCAL(0, 1);
     } else {
@@ -1087,6 +1155,41 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
     }
 #undef LOCAL
     return hipGetLastError();
+}
+
+// ---- single-sample forms
+hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s)
+{
+    XfwdDesc d{g, m, ms_map, S1, ms};
+    return launch_xfwd(&d, 1, s);
+}
+hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s)
+{
+    YDesc d{g, S1, S2};
+    return launch_yfwd(&d, 1, s);
+}
+hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s)
+{
+    ZDesc d{g, S2, K};
+    return launch_zconv(&d, 1, comp, s);
+}
+hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s)
+{
+    YDesc d{g, S2, S1};
+    return launch_yinv(&d, 1, s);
+}
+hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
+{
+    XinvDesc d{g, S1, Hd};
+    return launch_xinv(&d, 1, s);
+}
+
+hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
+                        const float *ms_map, const float *h_map, uint32_t terms, int mode, float dt,
+                        int renorm, float *out_m, float *out_h, int *flag, hipStream_t s)
+{
+    LocalDesc d{g, m, Hd, ms_map, h_map, out_m, out_h, p.h0, p.h1, p.h2};
+    return launch_local_batch(&d, 1, p, terms, mode, dt, renorm, flag, s);
 }
 
 hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,

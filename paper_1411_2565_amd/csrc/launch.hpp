@@ -24,6 +24,44 @@ struct LocalParams {
     float c1, c2;        // LLG: f = c1 m x H + c2 m x (m x H)
 };
 
+// Per-sample arguments of one pass.  A launch processes up to kMaxBatch
+// samples of one padded size; the descriptors travel by value in the kernel
+// arguments and blockIdx.z selects the sample.
+constexpr int kMaxBatch = 32;
+struct XfwdDesc {
+    Geo g;
+    const float *m;       // state [3][nz][ny][nx]
+    const float *ms_map;  // per-cell Ms or NULL
+    float2 *S1;           // x spectrum [3][nz][Hx][ny]
+    float ms;             // uniform Ms (M = ms m when no map; 1 for a plain field)
+};
+struct YDesc {
+    Geo g;
+    const float2 *in;
+    float2 *out;
+};
+struct ZDesc {
+    Geo g;
+    float2 *S2;      // [3][nz][Hx][Py], transformed in place
+    const float *K;  // tensor spectrum of this padded size
+};
+struct XinvDesc {
+    Geo g;
+    const float2 *S1;
+    float *Hd;  // H_demag [3][nz][ny][nx]
+};
+struct LocalDesc {
+    Geo g;
+    const float *m, *Hd, *ms_map, *h_map;
+    float *m_out;  // Euler step output (mode 1)
+    float *h_out;  // field output (mode 0)
+    float h0, h1, h2;  // uniform external field of this sample
+};
+template <typename D, int NB>
+struct Batch {
+    D s[NB];
+};
+
 // FP64 energy coefficients.
 struct EnergyParams {
     double A, Ku, u0, u1, u2, ms, h0, h1, h2;
@@ -37,7 +75,17 @@ constexpr int kEnergyBlocks = 512;
 
 hipError_t init_tables(hipStream_t s);
 
-// demag pipeline
+// demag pipeline, batched: `count` (1..kMaxBatch) samples sharing Px, Py, Pz
+hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s);
+hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s);
+hipError_t launch_zconv(const ZDesc *d, int count, bool compensated, hipStream_t s);
+hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s);
+hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s);
+// local terms + Euler step (mode 1) or field output (mode 0), batched
+hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &p, uint32_t terms, int mode,
+                              float dt, int renorm, int *flag, hipStream_t s);
+
+// single-sample forms
 hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s);
 hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s);
 hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool compensated, hipStream_t s);
