@@ -26,6 +26,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
+# HBM bytes per launch measured with rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (each scaled by what the same counter reads for a plain copy of known
+# size), keyed by kernel; valid only for the kernel sources whose SHA-256 is
+# recorded with them.  The summaries and commands are in profiles/.
+MEASURED_TRAFFIC = {}
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "fft.hpp", "launch.hpp"):
+        with open(os.path.join(ROOT, "paper_1411_2565_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    rec = MEASURED_TRAFFIC.get(kernel)
+    if rec and rec["source_sha"] == kernel_source_sha():
+        return rec["bytes_per_launch"]
+    return None
+
+
+def calibration_copy(nbytes=1 << 30, reps=3):
+    """A plain device copy of known size, for scaling the PMC byte counters."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
 
 def kernel_bytes(n, P):
     """Algorithmic HBM bytes per launch of each kernel (FP32 data, complex64
@@ -171,6 +203,8 @@ def main():
     ap.add_argument("--compensated", action="store_true", help="time the compensated spectral multiply")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (3 times) for PMC counter calibration")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -258,7 +292,7 @@ def main():
                    "cells": w.N, "dt": w.dt, "alpha": w.alpha, "Ms": w.Ms, "A": w.A,
                    "spectral_multiply": "compensated" if args.compensated else "plain"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)},
         "cpu_baseline": cpu,
         "step_bytes": step_bytes,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
@@ -268,6 +302,8 @@ def main():
         "batch": bat,
     }
     print(json.dumps(line), flush=True)
+    if args.calib_copy:
+        calibration_copy()
 
 
 if __name__ == "__main__":

@@ -45,6 +45,14 @@ constexpr int kThreads = 256;
 #ifndef MMK_ZC_E
 #define MMK_ZC_E 4
 #endif
+// LDS budget (KB) of a z-pass block: sets its columns per block
+#ifndef MMK_ZC_LDS_KB
+#define MMK_ZC_LDS_KB 32
+#endif
+// lines per block of the x passes (16: 128-byte runs in the transposed S1)
+#ifndef MMK_X_LPB
+#define MMK_X_LPB 16
+#endif
 
 __host__ __device__ constexpr int pow2floor(int v)
 {
@@ -78,8 +86,8 @@ struct YShape {
 template <int L>
 struct ZShape {
     static constexpr int E = L < MMK_ZC_E ? L : MMK_ZC_E, T = L / E;
-    static constexpr int CBmax = cmax(1, 32768 / (3 * 8 * lds_line(L)));
-    static constexpr int CB = cmin(kThreads / T, pow2floor(CBmax));
+    static constexpr int CBmax = cmax(1, (MMK_ZC_LDS_KB * 1024) / (3 * 8 * lds_line(L)));
+    static constexpr int CB = cmin(cmax(1, 1024 / T), pow2floor(CBmax));
     static constexpr int THREADS = T * CB;
     static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
 };
@@ -88,7 +96,7 @@ struct ZShape {
 template <int L>
 struct XShape {
     static constexpr int E = elems_per_thread(L), T = L / E;
-    static constexpr int LPB = cmax(1, cmin(64, 512 / T));
+    static constexpr int LPB = cmax(1, cmin(64, cmin(MMK_X_LPB, 1024 / T)));
     static constexpr int THREADS = T * LPB;
     static constexpr int LDS = LPB * lds_line(L);
 };

@@ -40,6 +40,18 @@ def test_bad_geometry_rejected_on_host():
         assert not ctx.value
 
 
+def test_batch_bad_sizes_rejected_on_host():
+    from paper_1411_2565_amd import binding
+    lib = binding.load()
+    b = ctypes.c_void_p()
+    for sizes, d in [([(64, 64, 1), (1, 8, 1)], (4e-9, 4e-9, 3e-9)), ([(600, 8, 1)], (4e-9, 4e-9, 3e-9)),
+                     ([(64, 64, 1)], (4e-9, -1.0, 3e-9))]:
+        arr = (ctypes.c_int32 * (3 * len(sizes)))(*[v for s in sizes for v in s])
+        assert lib.mm_batch_create(ctypes.byref(b), len(sizes), arr, *d, 0, None) == binding.MM_EINVAL
+        assert not b.value
+    assert lib.mm_batch_create(ctypes.byref(b), 0, None, 4e-9, 4e-9, 3e-9, 0, None) == binding.MM_EINVAL
+
+
 def test_null_arguments_rejected():
     from paper_1411_2565_amd import binding
     lib = binding.load()
