@@ -49,6 +49,24 @@ def measured_traffic(kernel):
     return None
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Achieved read+write GB/s of a plain device copy (the practical HBM
+    ceiling on this GPU), timed with events on the current stream."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
+
+
 def calibration_copy(nbytes=1 << 30, reps=3):
     """A plain device copy of known size, for scaling the PMC byte counters."""
     import torch
@@ -260,6 +278,7 @@ def main():
     step_bytes = sum(kb.values())
 
     sim.close()
+    copy_bw = copy_bandwidth()
     adj = None
     if not args.no_adjoint:
         print("bench: adjoint/forward ratio on the 128x128x4 film", file=sys.stderr, flush=True)
@@ -295,6 +314,7 @@ def main():
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)},
         "cpu_baseline": cpu,
         "step_bytes": step_bytes,
+        "copy_GBps": copy_bw,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": kernels,
         "tensor_build_s": round(t_build, 3),
