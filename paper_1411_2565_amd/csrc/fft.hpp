@@ -117,6 +117,15 @@ __host__ __device__ constexpr int stage_radix(int rem, int E) { return rem < E ?
 // (lds_line(L) complex).  Every thread of the block must take part: the
 // exchange uses block barriers.
 template <int L, int E, int NC, int Ns, bool INV>
+__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t);
+
+template <int L, int E, int NC, int Ns, bool INV>
+__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *(&lds)[NC], int t)
+{
+    fft_stages<L, E, NC, Ns, INV>(v, const_cast<float2 *const (&)[NC]>(lds), t);
+}
+
+template <int L, int E, int NC, int Ns, bool INV>
 __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
 {
     if constexpr (Ns < L) {

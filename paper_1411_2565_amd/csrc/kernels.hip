@@ -49,6 +49,10 @@ constexpr int kThreads = 256;
 #ifndef MMK_ZC_LDS_KB
 #define MMK_ZC_LDS_KB 32
 #endif
+// columns per z-pass thread: 1, or 2 to pair ky with Py - ky
+#ifndef MMK_ZC_PAIR
+#define MMK_ZC_PAIR 1
+#endif
 // lines per block of the x passes (16: 128-byte runs in the transposed S1)
 #ifndef MMK_X_LPB
 #define MMK_X_LPB 16
@@ -86,10 +90,11 @@ struct YShape {
 template <int L>
 struct ZShape {
     static constexpr int E = L < MMK_ZC_E ? L : MMK_ZC_E, T = L / E;
-    static constexpr int CBmax = cmax(1, (MMK_ZC_LDS_KB * 1024) / (3 * 8 * lds_line(L)));
+    static constexpr int PAIR = MMK_ZC_PAIR;  // columns per thread: 1, or 2 (ky and Py - ky)
+    static constexpr int CBmax = cmax(1, (MMK_ZC_LDS_KB * 1024) / (3 * PAIR * 8 * lds_line(L)));
     static constexpr int CB = cmin(cmax(1, 1024 / T), pow2floor(CBmax));
     static constexpr int THREADS = T * CB;
-    static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
+    static constexpr int LDS = nstages(L, E) > 1 ? 3 * PAIR * CB * lds_line(L) : 1;
 };
 // x passes: LPB lines of L = Px/2 complex per block (16 for 128-byte runs
 // in the transposed layout)
@@ -267,37 +272,53 @@ __device__ __forceinline__ float dot3_comp(float k0, float x0, float k1, float x
     return q + s;
 }
 
+// With MMK_ZC_PAIR = 2 a thread also takes the mirror column Py - ky of its
+// column ky (0 < ky < Py/2): both use the same octant row of K (odd-y
+// components with opposite signs), so each tensor value is loaded once.
 template <int L, bool COMP, int NB>
 __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B)
 {
     using S = ZShape<L>;
-    constexpr int E = S::E, T = S::T, CB = S::CB;
+    constexpr int E = S::E, T = S::T, CB = S::CB, PR = S::PAIR;
     extern __shared__ float2 sm[];
     const ZDesc &D = B.s[blockIdx.z];
     const Geo &g = D.g;
     float2 *__restrict__ S2 = D.S2;
     const float *__restrict__ K = D.K;
     const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
-    const int kx = blockIdx.y, ky = blockIdx.x * CB + col;
-    const bool ok = ky < g.Py;
-    const long long plane = (long long)g.Hx * g.Py;  // stride between z planes
-    float2 *base = S2 + (long long)kx * g.Py + ky;
-    float2 v[3][E];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int zz = t + q * T;
-            v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[((long long)c * g.nz + zz) * plane]
-                                                           : make_float2(0.f, 0.f);
-        }
-    float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
-                            sm + (2 * CB + col) * lds_line(L)};
-    reg_fft<L, false>(v, lds, t);
+    const int kx = blockIdx.y;
     const int hy = g.Py / 2, hz = g.Pz / 2;
-    const bool fy = ky > hy;
-    const int kyf = fy ? g.Py - ky : ky;
-    const float sy = fy ? -1.f : 1.f;
+    // column of each side: PR == 1: ky = slot; PR == 2: slot in [0, Hy) and its mirror
+    const int slot = blockIdx.x * CB + col;
+    int ky[PR];
+    bool ok[PR];
+    ky[0] = slot;
+    ok[0] = PR == 1 ? slot < g.Py : slot < g.Hy;
+    if constexpr (PR == 2) {
+        ky[1] = g.Py - slot;
+        ok[1] = slot > 0 && slot < hy;
+    }
+    const long long plane = (long long)g.Hx * g.Py;  // stride between z planes
+    float2 v[3 * PR][E];
+#pragma unroll
+    for (int sd = 0; sd < PR; ++sd) {
+        const float2 *base = S2 + (long long)kx * g.Py + ky[sd];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int zz = t + q * T;
+                v[3 * sd + c][q] = (q < half_elems(E) && ok[sd] && zz < g.nz)
+                                       ? base[((long long)c * g.nz + zz) * plane]
+                                       : make_float2(0.f, 0.f);
+            }
+    }
+    float2 *lds[3 * PR];
+#pragma unroll
+    for (int i = 0; i < 3 * PR; ++i) lds[i] = sm + (i * CB + col) * lds_line(L);
+    reg_fft<L, false>(v, lds, t);
+    const int kyf = (PR == 1 && slot > hy) ? g.Py - slot : slot;
+    const float sy0 = (PR == 1 && slot > hy) ? -1.f : 1.f;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int kz = t + q * T;
@@ -305,32 +326,43 @@ __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B
         const int kzf = fz ? g.Pz - kz : kz;
         const float sz = fz ? -1.f : 1.f;
         float k6[6] = {0, 0, 0, 0, 0, 0};
-        if (ok) {
+        if (ok[0]) {
             const float *kp = K + ((long long)kx * g.Hz + kzf) * 6 * g.Hy + kyf;
 #pragma unroll
             for (int p = 0; p < 6; ++p) k6[p] = kp[(long long)p * g.Hy];
         }
-        const float kxx = k6[0], kyy = k6[1], kzz = k6[2];
-        const float kxy = sy * k6[3], kxz = sz * k6[4], kyz = sy * sz * k6[5];
-        const float2 mx = v[0][q], my = v[1][q], mz = v[2][q];
-        if (COMP) {
-            v[0][q] = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
-            v[1][q] = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
-            v[2][q] = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
-        } else {
-            v[0][q] = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
-            v[1][q] = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
-            v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
+#pragma unroll
+        for (int sd = 0; sd < PR; ++sd) {
+            const float sy = sd == 0 ? sy0 : -1.f;
+            const float kxx = k6[0], kyy = k6[1], kzz = k6[2];
+            const float kxy = sy * k6[3], kxz = sz * k6[4], kyz = sy * sz * k6[5];
+            const float2 mx = v[3 * sd][q], my = v[3 * sd + 1][q], mz = v[3 * sd + 2][q];
+            float2 hx, hyv, hzv;
+            if (COMP) {
+                hx = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
+                hyv = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
+                hzv = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
+            } else {
+                hx = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
+                hyv = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
+                hzv = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
+            }
+            v[3 * sd][q] = hx;
+            v[3 * sd + 1][q] = hyv;
+            v[3 * sd + 2][q] = hzv;
         }
     }
     reg_fft<L, true>(v, lds, t);
-    if (ok) {
+#pragma unroll
+    for (int sd = 0; sd < PR; ++sd) {
+        if (!ok[sd]) continue;
+        float2 *base = S2 + (long long)kx * g.Py + ky[sd];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int q = 0; q < half_elems(E); ++q) {
                 const int zz = t + q * T;
-                if (zz < g.nz) base[((long long)c * g.nz + zz) * plane] = v[c][q];
+                if (zz < g.nz) base[((long long)c * g.nz + zz) * plane] = v[3 * sd + c][q];
             }
     }
 }
@@ -1119,7 +1151,8 @@ hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s)
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         using S = ZShape<LL>;                                                                 \
-        dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, count);                                   \
+        const int slots = S::PAIR == 2 ? g.Hy : g.Py;                                         \
+        dim3 grid((slots + S::CB - 1) / S::CB, g.Hx, count);                                  \
         const size_t lds = S::LDS * sizeof(float2);                                           \
         if (comp)                                                                             \
             MM_BATCH_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, LL, true);        \
