@@ -20,6 +20,10 @@ namespace mmk {
 
 constexpr int MAXL = 1024;  // longest line along any padded axis
 
+#ifndef MMK_TW_RECUR
+#define MMK_TW_RECUR 0
+#endif
+
 extern __device__ float2 g_tw[MAXL];
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -139,8 +143,16 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&l
             const int k = j & (Ns - 1);
             float2 w[R];
             if constexpr (Ns > 1) {
+#if MMK_TW_RECUR
+                // w^r by repeated multiplication from w and w^2 (two table loads)
+                w[1] = twiddle<INV>(k, Ns * R);
+                if constexpr (R > 2) w[2] = twiddle<INV>(2 * k, Ns * R);
+#pragma unroll
+                for (int r = 3; r < R; ++r) w[r] = cmul(w[r - 2], w[2]);
+#else
 #pragma unroll
                 for (int r = 1; r < R; ++r) w[r] = twiddle<INV>(r * k, Ns * R);
+#endif
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {

@@ -49,10 +49,6 @@ constexpr int kThreads = 256;
 #ifndef MMK_ZC_LDS_KB
 #define MMK_ZC_LDS_KB 32
 #endif
-// columns per z-pass thread: 1, or 2 to pair ky with Py - ky
-#ifndef MMK_ZC_PAIR
-#define MMK_ZC_PAIR 1
-#endif
 // lines per block of the x passes (16: 128-byte runs in the transposed S1)
 #ifndef MMK_X_LPB
 #define MMK_X_LPB 16
@@ -90,11 +86,10 @@ struct YShape {
 template <int L>
 struct ZShape {
     static constexpr int E = L < MMK_ZC_E ? L : MMK_ZC_E, T = L / E;
-    static constexpr int PAIR = MMK_ZC_PAIR;  // columns per thread: 1, or 2 (ky and Py - ky)
-    static constexpr int CBmax = cmax(1, (MMK_ZC_LDS_KB * 1024) / (3 * PAIR * 8 * lds_line(L)));
+    static constexpr int CBmax = cmax(1, (MMK_ZC_LDS_KB * 1024) / (3 * 8 * lds_line(L)));
     static constexpr int CB = cmin(cmax(1, 1024 / T), pow2floor(CBmax));
     static constexpr int THREADS = T * CB;
-    static constexpr int LDS = nstages(L, E) > 1 ? 3 * PAIR * CB * lds_line(L) : 1;
+    static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
 };
 // x passes: LPB lines of L = Px/2 complex per block (16 for 128-byte runs
 // in the transposed layout)
@@ -242,7 +237,8 @@ __global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
 // ------------------------------------------------------------------------
 // a3: z transform + tensor multiply + inverse z transform, per (kx, ky).
 // K holds the octant kx in [0,Hx), ky in [0,Hy), kz in [0,Hz) as
-// K[kx][kz][comp][ky], comp = xx, yy, zz, xy, xz, yz.  Components odd in y
+// K[kx][ky][kz][comp], comp = xx, yy, zz, xy, xz, yz: a block's 16 columns
+// read one contiguous chunk.  Components odd in y
 // (xy, yz) change sign for ky > Py/2, components odd in z (xz, yz) for
 // kz > Pz/2.  Compensated form: each of the six real dot products of three
 // terms is accumulated error-free (fma products, two-sum) and rounded once.
@@ -272,14 +268,22 @@ __device__ __forceinline__ float dot3_comp(float k0, float x0, float k1, float x
     return q + s;
 }
 
-// With MMK_ZC_PAIR = 2 a thread also takes the mirror column Py - ky of its
-// column ky (0 < ky < Py/2): both use the same octant row of K (odd-y
-// components with opposite signs), so each tensor value is loaded once.
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// ky tiles are ordered so that a tile and its mirror tile (whose columns use
+// the same octant rows of K) are 8 blocks apart, i.e. on the same XCD.
+__device__ __forceinline__ int zc_tile(int slot, int ntiles)
+{
+    if ((ntiles & 15) != 0) return slot;
+    const int grp = slot >> 4, r = slot & 15;
+    const int lower = grp * 8 + (r & 7);
+    return r < 8 ? lower : ntiles - 1 - lower;
+}
+
 template <int L, bool COMP, int NB>
 __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B)
 {
     using S = ZShape<L>;
-    constexpr int E = S::E, T = S::T, CB = S::CB, PR = S::PAIR;
+    constexpr int E = S::E, T = S::T, CB = S::CB;
     extern __shared__ float2 sm[];
     const ZDesc &D = B.s[blockIdx.z];
     const Geo &g = D.g;
@@ -287,82 +291,62 @@ __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B
     const float *__restrict__ K = D.K;
     const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
     const int kx = blockIdx.y;
-    const int hy = g.Py / 2, hz = g.Pz / 2;
-    // column of each side: PR == 1: ky = slot; PR == 2: slot in [0, Hy) and its mirror
-    const int slot = blockIdx.x * CB + col;
-    int ky[PR];
-    bool ok[PR];
-    ky[0] = slot;
-    ok[0] = PR == 1 ? slot < g.Py : slot < g.Hy;
-    if constexpr (PR == 2) {
-        ky[1] = g.Py - slot;
-        ok[1] = slot > 0 && slot < hy;
-    }
+    const int ky = zc_tile(blockIdx.x, gridDim.x) * CB + col;
+    const bool ok = ky < g.Py;
     const long long plane = (long long)g.Hx * g.Py;  // stride between z planes
-    float2 v[3 * PR][E];
+    float2 *base = S2 + (long long)kx * g.Py + ky;
+    float2 v[3][E];
 #pragma unroll
-    for (int sd = 0; sd < PR; ++sd) {
-        const float2 *base = S2 + (long long)kx * g.Py + ky[sd];
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int q = 0; q < E; ++q) {
-                const int zz = t + q * T;
-                v[3 * sd + c][q] = (q < half_elems(E) && ok[sd] && zz < g.nz)
-                                       ? base[((long long)c * g.nz + zz) * plane]
-                                       : make_float2(0.f, 0.f);
-            }
-    }
-    float2 *lds[3 * PR];
-#pragma unroll
-    for (int i = 0; i < 3 * PR; ++i) lds[i] = sm + (i * CB + col) * lds_line(L);
+        for (int q = 0; q < E; ++q) {
+            const int zz = t + q * T;
+            v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[((long long)c * g.nz + zz) * plane]
+                                                           : make_float2(0.f, 0.f);
+        }
+    float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
+                            sm + (2 * CB + col) * lds_line(L)};
     reg_fft<L, false>(v, lds, t);
-    const int kyf = (PR == 1 && slot > hy) ? g.Py - slot : slot;
-    const float sy0 = (PR == 1 && slot > hy) ? -1.f : 1.f;
+    const int hy = g.Py / 2, hz = g.Pz / 2;
+    const bool fy = ky > hy;
+    const int kyf = fy ? g.Py - ky : ky;
+    const float sy = fy ? -1.f : 1.f;
+    // this column's octant entries: K[kx][kyf][kz][6], contiguous over kz
+    const float *kcol = K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int kz = t + q * T;
         const bool fz = kz > hz;
         const int kzf = fz ? g.Pz - kz : kz;
         const float sz = fz ? -1.f : 1.f;
-        float k6[6] = {0, 0, 0, 0, 0, 0};
-        if (ok[0]) {
-            const float *kp = K + ((long long)kx * g.Hz + kzf) * 6 * g.Hy + kyf;
-#pragma unroll
-            for (int p = 0; p < 6; ++p) k6[p] = kp[(long long)p * g.Hy];
+        float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
+        if (ok) {
+            const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
+            k01 = kp[0];
+            k23 = kp[1];
+            k45 = kp[2];
         }
-#pragma unroll
-        for (int sd = 0; sd < PR; ++sd) {
-            const float sy = sd == 0 ? sy0 : -1.f;
-            const float kxx = k6[0], kyy = k6[1], kzz = k6[2];
-            const float kxy = sy * k6[3], kxz = sz * k6[4], kyz = sy * sz * k6[5];
-            const float2 mx = v[3 * sd][q], my = v[3 * sd + 1][q], mz = v[3 * sd + 2][q];
-            float2 hx, hyv, hzv;
-            if (COMP) {
-                hx = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
-                hyv = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
-                hzv = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
-            } else {
-                hx = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
-                hyv = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
-                hzv = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
-            }
-            v[3 * sd][q] = hx;
-            v[3 * sd + 1][q] = hyv;
-            v[3 * sd + 2][q] = hzv;
+        const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
+        const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
+        const float2 mx = v[0][q], my = v[1][q], mz = v[2][q];
+        if (COMP) {
+            v[0][q] = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
+            v[1][q] = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
+            v[2][q] = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
+        } else {
+            v[0][q] = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
+            v[1][q] = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
+            v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
         }
     }
     reg_fft<L, true>(v, lds, t);
-#pragma unroll
-    for (int sd = 0; sd < PR; ++sd) {
-        if (!ok[sd]) continue;
-        float2 *base = S2 + (long long)kx * g.Py + ky[sd];
+    if (ok) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int q = 0; q < half_elems(E); ++q) {
                 const int zz = t + q * T;
-                if (zz < g.nz) base[((long long)c * g.nz + zz) * plane] = v[3 * sd + c][q];
+                if (zz < g.nz) base[((long long)c * g.nz + zz) * plane] = v[c][q];
             }
     }
 }
@@ -1022,11 +1006,11 @@ __global__ __launch_bounds__(kThreads) void k_pack(Geo g, const double *__restri
     const long long total = (long long)g.Hx * g.Hy * g.Hz;
     const long long idx = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (idx >= total) return;
-    // T is [Hz][Hy][Hx]; K is [Hx][Hz][6][Hy]
+    // T is [Hz][Hy][Hx]; K is [Hx][Hy][Hz][6]
     const int kx = (int)(idx % g.Hx);
     const long long r = idx / g.Hx;
     const int ky = (int)(r % g.Hy), kz = (int)(r / g.Hy);
-    K[(((long long)kx * g.Hz + kz) * 6 + comp) * g.Hy + ky] = (float)(scale * T[idx]);
+    K[(((long long)kx * g.Hy + ky) * g.Hz + kz) * 6 + comp] = (float)(scale * T[idx]);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1151,8 +1135,7 @@ hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s)
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         using S = ZShape<LL>;                                                                 \
-        const int slots = S::PAIR == 2 ? g.Hy : g.Py;                                         \
-        dim3 grid((slots + S::CB - 1) / S::CB, g.Hx, count);                                  \
+        dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, count);                                   \
         const size_t lds = S::LDS * sizeof(float2);                                           \
         if (comp)                                                                             \
             MM_BATCH_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, LL, true);        \
