@@ -12,7 +12,8 @@
 //
 // Forward uses exp(-2 pi i jk/L); the inverse exp(+2 pi i jk/L), unnormalised.
 // Twiddles come from one table of exp(-2 pi i t / MAXL), t < MAXL, rounded
-// once from FP64, so every twiddle is within 0.5 ulp.
+// once from FP64 (within 0.5 ulp); a radix-R butterfly loads w and w^2 and
+// forms the other powers with at most three complex products (a few ulp).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -20,9 +21,6 @@ namespace mmk {
 
 constexpr int MAXL = 1024;  // longest line along any padded axis
 
-#ifndef MMK_TW_RECUR
-#define MMK_TW_RECUR 0
-#endif
 
 extern __device__ float2 g_tw[MAXL];
 
@@ -143,16 +141,12 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&l
             const int k = j & (Ns - 1);
             float2 w[R];
             if constexpr (Ns > 1) {
-#if MMK_TW_RECUR
-                // w^r by repeated multiplication from w and w^2 (two table loads)
+                // w^r from two table loads (w, w^2) and at most three complex
+                // products: table loads, not arithmetic, bound these passes
                 w[1] = twiddle<INV>(k, Ns * R);
                 if constexpr (R > 2) w[2] = twiddle<INV>(2 * k, Ns * R);
 #pragma unroll
                 for (int r = 3; r < R; ++r) w[r] = cmul(w[r - 2], w[2]);
-#else
-#pragma unroll
-                for (int r = 1; r < R; ++r) w[r] = twiddle<INV>(r * k, Ns * R);
-#endif
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {

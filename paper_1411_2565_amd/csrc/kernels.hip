@@ -49,6 +49,10 @@ constexpr int kThreads = 256;
 #ifndef MMK_ZC_LDS_KB
 #define MMK_ZC_LDS_KB 32
 #endif
+// lines per thread group in the y passes
+#ifndef MMK_Y_NC
+#define MMK_Y_NC 1
+#endif
 // lines per block of the x passes (16: 128-byte runs in the transposed S1)
 #ifndef MMK_X_LPB
 #define MMK_X_LPB 16
@@ -79,7 +83,10 @@ __host__ __device__ constexpr int nstages(int L, int E)
 // y passes: one line of L per T = L/E threads, 256 threads per block
 template <int L>
 struct YShape {
-    static constexpr int E = elems_per_thread(L), T = L / E, LPB = kThreads / T;
+    static constexpr int E = elems_per_thread(L), T = L / E;
+    static constexpr int NC = MMK_Y_NC;       // lines per thread group
+    static constexpr int G = kThreads / T;    // thread groups per block
+    static constexpr int LPB = G * NC;        // lines per block
     static constexpr int LDS = LPB * lds_line(L);
 };
 // z pass: CB columns of the three components per block
@@ -98,8 +105,16 @@ struct XShape {
     static constexpr int E = elems_per_thread(L), T = L / E;
     static constexpr int LPB = cmax(1, cmin(64, cmin(MMK_X_LPB, 1024 / T)));
     static constexpr int THREADS = T * LPB;
-    static constexpr int LDS = LPB * lds_line(L);
+    static constexpr int LDS = LPB * lds_line(L) + L + 1;  // + twiddles exp(-2 pi i k/Px), k <= L
 };
+
+// exp(-2 pi i k / (2L)) for k in [0, L] into LDS (first barrier of the caller
+// makes it visible)
+template <int L, int THREADS>
+__device__ __forceinline__ void load_half_twiddles(float2 *tw)
+{
+    for (int k = threadIdx.x; k <= L; k += THREADS) tw[k] = twiddle<false>(k, 2 * L);
+}
 
 // ------------------------------------------------------------------------
 // a1: x-forward real FFT.  A real line x[0..Px) (nx non-zeros) is packed as
@@ -151,6 +166,8 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Batch<XfwdDesc, NB>
         }
         v[0][q] = a;
     }
+    float2 *const tw = sm + LPB * LD;
+    load_half_twiddles<L, S::THREADS>(tw);
     float2 *const lds[1] = {sm + ll * LD};
     reg_fft<L, false>(v, lds, t);
 #pragma unroll
@@ -166,7 +183,7 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Batch<XfwdDesc, NB>
         const float2 zc = cconj(Z[(L - kx) & (L - 1)]);
         const float2 Ev = cscale(cadd(zk, zc), 0.5f);
         const float2 Od = mul_mi<false>(cscale(csub(zk, zc), 0.5f));
-        out[(long long)kx * g.ny + yl] = cadd(Ev, cmul(twiddle<false>(kx, 2 * L), Od));
+        out[(long long)kx * g.ny + yl] = cadd(Ev, cmul(tw[kx], Od));
     }
 }
 
@@ -178,29 +195,38 @@ template <int L, int NB>
 __global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
 {
     using S = YShape<L>;
-    constexpr int E = S::E, T = S::T, LPB = S::LPB;
+    constexpr int E = S::E, T = S::T, NC = S::NC, LPB = S::LPB;
     extern __shared__ float2 sm[];
     const YDesc &D = B.s[blockIdx.z];
     const Geo &g = D.g;
     const float2 *__restrict__ S1 = D.in;
     float2 *__restrict__ S2 = D.out;
-    if ((long long)blockIdx.x * LPB >= 3LL * g.nz * g.Hx) return;
-    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
-    const long long line = (long long)blockIdx.x * LPB + ll;
-    const bool ok = line < 3LL * g.nz * g.Hx;
-    const float2 *in = S1 + line * g.ny;
-    float2 v[1][E];
+    const long long nlines = 3LL * g.nz * g.Hx;
+    if ((long long)blockIdx.x * LPB >= nlines) return;
+    const int gi = threadIdx.x / T, t = threadIdx.x - gi * T;
+    float2 v[NC][E];
+    float2 *lds[NC];
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int y = t + q * T;
-        v[0][q] = (q < half_elems(E) && ok && y < g.ny) ? in[y] : make_float2(0.f, 0.f);
+    for (int c = 0; c < NC; ++c) {
+        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        const bool ok = line < nlines;
+        const float2 *in = S1 + line * g.ny;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int y = t + q * T;
+            v[c][q] = (q < half_elems(E) && ok && y < g.ny) ? in[y] : make_float2(0.f, 0.f);
+        }
+        lds[c] = sm + (gi * NC + c) * lds_line(L);
     }
-    float2 *const lds[1] = {sm + ll * lds_line(L)};
     reg_fft<L, false>(v, lds, t);
-    if (ok) {
-        float2 *out = S2 + line * L;
 #pragma unroll
-        for (int q = 0; q < E; ++q) out[t + q * T] = v[0][q];
+    for (int c = 0; c < NC; ++c) {
+        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        if (line < nlines) {
+            float2 *out = S2 + line * L;
+#pragma unroll
+            for (int q = 0; q < E; ++q) out[t + q * T] = v[c][q];
+        }
     }
 }
 
@@ -208,28 +234,37 @@ template <int L, int NB>
 __global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
 {
     using S = YShape<L>;
-    constexpr int E = S::E, T = S::T, LPB = S::LPB;
+    constexpr int E = S::E, T = S::T, NC = S::NC, LPB = S::LPB;
     extern __shared__ float2 sm[];
     const YDesc &D = B.s[blockIdx.z];
     const Geo &g = D.g;
     const float2 *__restrict__ S2 = D.in;
     float2 *__restrict__ S1 = D.out;
-    if ((long long)blockIdx.x * LPB >= 3LL * g.nz * g.Hx) return;
-    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
-    const long long line = (long long)blockIdx.x * LPB + ll;
-    const bool ok = line < 3LL * g.nz * g.Hx;
-    const float2 *in = S2 + line * L;
-    float2 v[1][E];
+    const long long nlines = 3LL * g.nz * g.Hx;
+    if ((long long)blockIdx.x * LPB >= nlines) return;
+    const int gi = threadIdx.x / T, t = threadIdx.x - gi * T;
+    float2 v[NC][E];
+    float2 *lds[NC];
 #pragma unroll
-    for (int q = 0; q < E; ++q) v[0][q] = ok ? in[t + q * T] : make_float2(0.f, 0.f);
-    float2 *const lds[1] = {sm + ll * lds_line(L)};
+    for (int c = 0; c < NC; ++c) {
+        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        const bool ok = line < nlines;
+        const float2 *in = S2 + line * L;
+#pragma unroll
+        for (int q = 0; q < E; ++q) v[c][q] = ok ? in[t + q * T] : make_float2(0.f, 0.f);
+        lds[c] = sm + (gi * NC + c) * lds_line(L);
+    }
     reg_fft<L, true>(v, lds, t);
-    if (ok) {
-        float2 *out = S1 + line * g.ny;
 #pragma unroll
-        for (int q = 0; q < half_elems(E); ++q) {
-            const int y = t + q * T;
-            if (y < g.ny) out[y] = v[0][q];
+    for (int c = 0; c < NC; ++c) {
+        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        if (line < nlines) {
+            float2 *out = S1 + line * g.ny;
+#pragma unroll
+            for (int q = 0; q < half_elems(E); ++q) {
+                const int y = t + q * T;
+                if (y < g.ny) out[y] = v[c][q];
+            }
         }
     }
 }
@@ -371,6 +406,8 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Batch<XinvDesc, NB>
     if (z >= g.nz || y0 >= g.ny) return;
     const int nl = min(LPB, g.ny - y0);
     const float2 *in = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
+    float2 *const tw = sm + LPB * LD;
+    load_half_twiddles<L, S::THREADS>(tw);
     for (int idx = threadIdx.x; idx < (L + 1) * LPB; idx += S::THREADS) {
         const int kx = idx / LPB, yl = idx - kx * LPB;
         sm[yl * LD + kx] = yl < nl ? in[(long long)kx * g.ny + yl] : make_float2(0.f, 0.f);
@@ -385,7 +422,7 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Batch<XinvDesc, NB>
             const int k = t + q * T;
             const float2 xk = X[k], xc = cconj(X[L - k]);
             const float2 Ev = cadd(xk, xc);
-            const float2 Od = cmul(csub(xk, xc), twiddle<true>(k, 2 * L));
+            const float2 Od = cmul(csub(xk, xc), cconj(tw[k]));
             v[0][q] = cadd(Ev, mul_mi<true>(Od));
         }
     }
