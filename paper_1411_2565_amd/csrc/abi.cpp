@@ -475,24 +475,35 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m, float *h, uint32_t terms)
 
 namespace {
 
-// enqueue nsteps Euler steps on the context's stream (no checks)
-mm_status enqueue_steps(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
+// Enqueue nsteps Euler steps: step s reads src(s), writes the new state to
+// dst(s) and, when hd(s) is not null, H_demag of src(s) there.  mm_step_llg
+// and mm_forward_store both go through here, so a replay from a stored state
+// reproduces the forward run bit for bit.
+template <class Src, class Dst, class HdOut>
+mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src src, Dst dst, HdOut hd)
 {
     const mmk::LocalParams p = local_params(c);
     const bool comp = flags & MM_F_COMPENSATED;
     const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
-    float *buf[2] = {m, c->at<float>(c->o_mtmp)};
     int *flag = c->at<int>(c->o_flag);
     for (int64_t s = 0; s < nsteps; ++s) {
-        const float *src = buf[s & 1];
-        float *dst = buf[(s + 1) & 1];
         float *Hd = nullptr;
-        MM_TRY(demag(c, src, comp, &Hd));
+        MM_TRY(demag(c, src(s), comp, &Hd, hd(s)));
         MM_TRY(timed(c, MM_K_LOCAL, "llg step", [&] {
-            return mmk::launch_local(c->g, p, src, Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt, renorm,
-                                     dst, nullptr, flag, c->stream);
+            return mmk::launch_local(c->g, p, src(s), Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt,
+                                     renorm, dst(s), nullptr, flag, c->stream);
         }));
     }
+    return MM_OK;
+}
+
+// nsteps Euler steps of m in place, through the context's state buffer
+mm_status enqueue_steps(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t flags)
+{
+    float *buf[2] = {m, c->at<float>(c->o_mtmp)};
+    MM_TRY(run_steps(
+        c, nsteps, dt, flags, [&](int64_t s) { return buf[s & 1]; }, [&](int64_t s) { return buf[(s + 1) & 1]; },
+        [](int64_t) { return (float *)nullptr; }));
     if (nsteps & 1)
         MM_TRY(hipcheck(c, hipMemcpyAsync(m, buf[1], sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice, c->stream),
                         "copy back state"));
@@ -570,23 +581,13 @@ mm_status mm_forward_store(mm_ctx *c, float *m, int64_t nsteps, double dt, uint3
         return fail(c, MM_EINVAL, "trajectory buffers must be 16-byte aligned device pointers");
     MM_TRY(set_device(c));
     const size_t S = 3 * (size_t)c->g.N;
-    const mmk::LocalParams p = local_params(c);
-    const bool comp = flags & MM_F_COMPENSATED;
-    const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
-    int *flag = c->at<int>(c->o_flag);
     if (nsteps > 0)
         MM_TRY(hipcheck(c, hipMemcpyAsync(m_traj, m, sizeof(float) * S, hipMemcpyDeviceToDevice, c->stream),
                         "store state"));
-    for (int64_t s = 0; s < nsteps; ++s) {
-        const float *src = m_traj + (size_t)s * S;
-        float *dst = (s + 1 < nsteps) ? m_traj + (size_t)(s + 1) * S : m;
-        float *Hd = nullptr;
-        MM_TRY(demag(c, src, comp, &Hd, hd_traj + (size_t)s * S));
-        MM_TRY(timed(c, MM_K_LOCAL, "llg step", [&] {
-            return mmk::launch_local(c->g, p, src, Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt, renorm,
-                                     dst, nullptr, flag, c->stream);
-        }));
-    }
+    MM_TRY(run_steps(
+        c, nsteps, dt, flags, [&](int64_t s) { return m_traj + (size_t)s * S; },
+        [&](int64_t s) { return (s + 1 < nsteps) ? m_traj + (size_t)(s + 1) * S : m; },
+        [&](int64_t s) { return hd_traj + (size_t)s * S; }));
     return MM_OK;
 }
 

@@ -175,9 +175,13 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Batch<XfwdDesc, NB>
     __syncthreads();
     float2 *out = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
     const int nl = min(LPB, g.ny - y0);
-    for (int idx = threadIdx.x; idx < (L + 1) * LPB; idx += S::THREADS) {
+    // compile-time trip count: every iteration's loads/stores issue together
+    constexpr int NIT = ((L + 1) * LPB + S::THREADS - 1) / S::THREADS;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * S::THREADS;
         const int kx = idx / LPB, yl = idx - kx * LPB;
-        if (yl >= nl) continue;
+        if (idx >= (L + 1) * LPB || yl >= nl) continue;
         const float2 *Z = sm + yl * LD;
         const float2 zk = Z[kx & (L - 1)];
         const float2 zc = cconj(Z[(L - kx) & (L - 1)]);
@@ -408,9 +412,19 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Batch<XinvDesc, NB>
     const float2 *in = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
     float2 *const tw = sm + LPB * LD;
     load_half_twiddles<L, S::THREADS>(tw);
-    for (int idx = threadIdx.x; idx < (L + 1) * LPB; idx += S::THREADS) {
+    constexpr int NIT = ((L + 1) * LPB + S::THREADS - 1) / S::THREADS;
+    float2 tile[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * S::THREADS;
         const int kx = idx / LPB, yl = idx - kx * LPB;
-        sm[yl * LD + kx] = yl < nl ? in[(long long)kx * g.ny + yl] : make_float2(0.f, 0.f);
+        tile[it] = (idx < (L + 1) * LPB && yl < nl) ? in[(long long)kx * g.ny + yl] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * S::THREADS;
+        const int kx = idx / LPB, yl = idx - kx * LPB;
+        if (idx < (L + 1) * LPB) sm[yl * LD + kx] = tile[it];
     }
     __syncthreads();
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
