@@ -210,6 +210,88 @@ def batch_rate(binding, steps=5000, single_steps=200):
             "speedup": round((cells * steps / tb) / (cells * single_steps / ts), 2)}
 
 
+# Table 1 of the paper: ms per Euler step on an AMD Radeon HD 7970 GHz
+# Edition (C++ AMP), N x N x N cubes.  Context only: other hardware.
+PAPER_TABLE1_MS = {8: 1.95, 16: 2.723, 32: 3.151, 64: 6.558, 128: 26.34}
+
+
+def timed_steps(sim, m, steps, dt, flags):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(m, steps, dt, flags)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def sweep_row(binding, w):
+    import torch
+    from paper_1411_2565_amd import workloads
+    m0, _ = workloads.inputs(w)
+    t = time.perf_counter()
+    sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=w.Ku, u=w.u, alpha=w.alpha, device=0)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t
+    m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+    steps = 32 * max(4, min(64, int(6e7 / w.N)))
+    sim.step(m, 64, w.dt, binding.MM_F_GRAPH)
+    sim.step(m, 32, w.dt)
+    te = timed_steps(sim, m, steps, w.dt, 0)
+    tg = timed_steps(sim, m, steps, w.dt, binding.MM_F_GRAPH)
+    binding.mm_kernel_timing(sim.ctx, True)
+    sim.step(m, 20, w.dt)
+    kt = binding.mm_kernel_times(sim.ctx)
+    binding.mm_kernel_timing(sim.ctx, False)
+    sim.sync()
+    sim.close()
+    N = w.n[0]
+    return {"n": N, "cells": w.N, "padded": [padded(v) for v in w.n], "steps": steps,
+            "us_per_step": round(1e6 * te / steps, 2), "us_per_step_graph": round(1e6 * tg / steps, 2),
+            "cell_steps_per_s": w.N * steps / min(te, tg), "tensor_build_s": round(t_build, 3),
+            "kernels_us": {k: round(1e3 * t / c, 2) for k, (t, c) in kt.items() if c},
+            "paper_ms_per_step": PAPER_TABLE1_MS.get(N)}
+
+
+def size_sweep(binding, sizes=None):
+    """Per-step time on Table 1's N^3 cubes (A = 1e-11 J/m, Ms = 1e6 A/m,
+    anisotropy field 1e5 A/m along x, 5 nm cells, alpha = 0.5, dt = 1e-13 s,
+    random initial state): eager launches and 32-step hipGraph chunks."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    rows = []
+    s = torch.cuda.Stream()  # graph capture needs a non-default stream
+    for N in sizes or workloads.TABLE1_SIZES:
+        with torch.cuda.stream(s):
+            rows.append(sweep_row(binding, workloads.table1_cube(N)))
+        torch.cuda.empty_cache()
+    return {"workload": "N^3 cubes, 5 nm cells, A=1e-11, Ms=1e6, H_K=1e5 A/m along x, alpha=0.5, dt=1e-13",
+            "paper_hardware": "AMD Radeon HD 7970 GHz Edition (Table 1)", "rows": rows}
+
+
+def sp4_rate(binding, steps=2048):
+    """Standard problem #4 film as the paper runs it (500 x 125 x 3 cells of
+    1 nm, padded 1024 x 256 x 8, alpha = 0.02, field 1, dt = 1e-13 s as in the
+    paper's input file): per-step time, eager and hipGraph."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    w = workloads.SP4_500x125x3
+    m0, _ = workloads.inputs(w)
+    h = workloads.field_mT(workloads.SP4_FIELD1_mT)
+    s = torch.cuda.Stream()  # graph capture needs a non-default stream
+    with torch.cuda.stream(s):
+        sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=tuple(h), device=0)
+        m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+        sim.step(m, 64, w.dt, binding.MM_F_GRAPH)
+        sim.step(m, 32, w.dt)
+        te = timed_steps(sim, m, steps, w.dt, 0)
+        tg = timed_steps(sim, m, steps, w.dt, binding.MM_F_GRAPH)
+        sim.sync()
+        sim.close()
+    return {"workload": "film 500x125x3, 1 nm cells, padded 1024x256x8, alpha=0.02, field 1, dt=1e-13",
+            "steps": steps, "us_per_step": round(1e6 * te / steps, 2), "us_per_step_graph": round(1e6 * tg / steps, 2),
+            "cell_steps_per_s": w.N * steps / min(te, tg)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +303,7 @@ def main():
     ap.add_argument("--compensated", action="store_true", help="time the compensated spectral multiply")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the N^3 cube size sweep and the SP4 film")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (3 times) for PMC counter calibration")
     args = ap.parse_args()
@@ -289,6 +372,13 @@ def main():
         print("bench: batched films", file=sys.stderr, flush=True)
         bat = batch_rate(binding)
 
+    sweep = sp4 = None
+    if not args.no_sweep:
+        print("bench: N^3 cube size sweep", file=sys.stderr, flush=True)
+        sweep = size_sweep(binding)
+        print("bench: standard problem #4 film", file=sys.stderr, flush=True)
+        sp4 = sp4_rate(binding)
+
     cpu = None
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
@@ -320,6 +410,8 @@ def main():
         "tensor_build_s": round(t_build, 3),
         "adjoint": adj,
         "batch": bat,
+        "size_sweep": sweep,
+        "sp4": sp4,
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:

@@ -84,6 +84,39 @@ FILM_128x128x4 = Workload("film 128x128x4, 5 nm cubes (adjoint)", (128, 128, 4),
                           init="near_uniform", field_mT=20.0)
 
 
+# Table 1's benchmark: N x N x N cubes, A = 1e-11 J/m, Ms = 1e6 A/m and an
+# anisotropy field 2 Ku / (mu0 Ms) = 1e5 A/m (Sec. 4).  The paper states no
+# cell size, axis, damping or time step: 5 nm cubes, easy axis x, alpha = 0.5
+# (the sample relaxes) and dt = 1e-13 s (stable for these cells) are used.
+TABLE1_SIZES = (8, 16, 32, 64, 128, 256)
+
+
+def table1_cube(N: int) -> Workload:
+    Ms, HK = 1.0e6, 1.0e5
+    return Workload(f"cube {N}x{N}x{N}, 5 nm cells", (N, N, N), (5e-9,) * 3,
+                    Ms=Ms, A=1.0e-11, alpha=0.5, dt=1e-13, nsteps=1000,
+                    Ku=0.5 * MU0 * Ms * HK, u=(1.0, 0.0, 0.0))
+
+
+# Standard problem #4 as the paper runs it (Sec. 4): 500 x 125 x 3 cells of
+# 1 nm, A = 1.3e-11 J/m, Ms = 8.0e5 A/m, no anisotropy; relaxed at large
+# damping, then reversed at alpha = 0.02 under field 1 or field 2 (mT, as
+# B = mu0 H).  The paper's input file uses dt = 1e-13 s, far above the
+# explicit Euler limit for 1 nm cells at alpha = 0.02 (about 6e-16 s): that dt
+# serves for timing only; trajectories are compared at SP4_STABLE_DT.
+SP4_FIELD1_mT = (-24.6, 4.3, 0.0)
+SP4_FIELD2_mT = (-35.5, -6.3, 0.0)
+SP4_STABLE_DT = 2e-16
+SP4_500x125x3 = Workload("film 500x125x3, 1 nm cells (standard problem #4)", (500, 125, 3), (1e-9,) * 3,
+                         Ms=8.0e5, A=1.3e-11, alpha=0.02, dt=1e-13, nsteps=10000,
+                         init="near_uniform")
+
+
+def field_mT(b_mT):
+    """A field given as B = mu0 H in mT, returned as H in A/m."""
+    return np.asarray(b_mT, dtype=np.float64) * (1e-3 / MU0)
+
+
 def initial_m(w: Workload):
     """m0 for a workload, and the rng positioned after the m0 draw."""
     rng = np.random.default_rng(w.seed)

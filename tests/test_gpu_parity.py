@@ -131,6 +131,23 @@ def test_trajectory_block16_100_steps(gpu_lib):
     assert torch.isfinite(m).all()
 
 
+def test_trajectory_block64x64x8_100_steps(gpu_lib):
+    """Standalone 64x64x8 sample with the large block's material (seed 1):
+    100 steps against the oracle's full direct-sum trajectory."""
+    w = workloads.BLOCK_64x64x8
+    m0, _ = workloads.inputs(w)
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    m = gpu(m0)
+    mf = host(m)
+    sim.step(m, w.nsteps, w.dt)
+    sim.sync()
+    mo = oracle.Problem(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha).run(mf, w.nsteps, w.dt)
+    e = rel(host(m), mo)
+    print(f"trajectory 64x64x8, 100 steps: rel L2 {e:.2e}")
+    assert e < 1e-4
+    sim.close()
+
+
 def test_trajectory_split_calls_equal_one_call(gpu_lib):
     """Odd/even step counts go through the internal double buffer: 37 steps
     in one call must equal 20 + 17 steps bit for bit."""

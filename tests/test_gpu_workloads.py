@@ -1,0 +1,134 @@
+"""GPU parity on the paper's other workloads: Table 1's N^3 cubes and the
+standard problem #4 film (Sec. 4), against the FP64 oracle.
+
+Tolerances as for the other parity tests: H_eff within 1e-5 relative L2, the
+state after 100 Euler steps within 1e-4.  At full size the oracle evaluates
+sampled cells only: H_demag by direct sum over every source, and one whole
+Euler step (all field terms) at those cells; the one-step check compares the
+increments m1 - m0, which carry the field error undiluted.
+
+Paper: Zhu, arXiv:1411.2565, Sec. 3 (method), Sec. 4 (Table 1 benchmark
+material; standard problem #4 geometry, material and fields).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1411_2565_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
+
+
+def gpu(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def make(gpu_lib, w, h=(0.0, 0.0, 0.0)):
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=w.Ku, u=w.u, alpha=w.alpha, hext=tuple(h))
+    P = oracle.Problem(w.n, w.d, Ms=w.Ms, A=w.A, Ku=w.Ku, u=w.u, alpha=w.alpha, hext=np.asarray(h))
+    return sim, P
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_table1_cube_heff_and_trajectory(gpu_lib, N):
+    w = workloads.table1_cube(N)
+    m0, _ = workloads.inputs(w)
+    sim, P = make(gpu_lib, w)
+    m = gpu(m0)
+    mf = host(m)
+    e = rel(host(sim.heff(m)), P.heff(mf))
+    sim.step(m, 100, w.dt)
+    sim.sync()
+    et = rel(host(m), P.run(mf, 100, w.dt))
+    print(f"cube {N}^3: H_eff rel L2 {e:.2e}, 100 steps rel L2 {et:.2e}")
+    assert e < 1e-5
+    assert et < 1e-4
+    sim.close()
+
+
+def test_table1_cube32_heff(gpu_lib):
+    w = workloads.table1_cube(32)
+    m0, _ = workloads.inputs(w)
+    sim, P = make(gpu_lib, w)
+    m = gpu(m0)
+    e = rel(host(sim.heff(m)), P.heff(host(m)))
+    print(f"cube 32^3: H_eff rel L2 {e:.2e}")
+    assert e < 1e-5
+    sim.close()
+
+
+def sampled_checks(gpu_lib, w, h, dt, nobs, seed, label):
+    """H_demag at sampled cells, and one Euler step at the same cells, on a
+    workload too large for the oracle's full direct sum every step."""
+    m0, _ = workloads.inputs(w)
+    sim, P = make(gpu_lib, w, h)
+    m = gpu(m0)
+    mf = host(m)
+    N = w.N
+    rng = np.random.default_rng(seed)
+    nx, ny = w.n[0], w.n[1]
+    corners = [0, nx - 1, nx * ny - 1, N - nx, N - 1]
+    obs = np.unique(np.concatenate([corners, rng.choice(N, nobs, replace=False)]))
+    Hd = host(sim.heff(m, gpu_lib.MM_T_DEMAG)).reshape(3, -1)
+    e_d = rel(Hd[:, obs], P.demag_observers(mf, obs))
+    sim.step(m, 1, dt)
+    sim.sync()
+    m1 = host(m).reshape(3, -1)[:, obs]
+    m1o = P.step_cells(mf, obs, dt)
+    m0s = mf.reshape(3, -1)[:, obs]
+    e_s = rel(m1 - m0s, m1o - m0s)
+    print(f"{label}: sampled H_demag rel L2 {e_d:.2e}, one-step increment rel L2 {e_s:.2e}")
+    assert e_d < 1e-5
+    assert e_s < 1e-5
+    sim.close()
+
+
+@pytest.mark.parametrize("N,nobs", [(64, 512), (128, 512), (256, 256)])
+def test_table1_cube_sampled(gpu_lib, N, nobs):
+    """The larger cubes of the sweep, padded up to 512^3 (z FFT of 512)."""
+    w = workloads.table1_cube(N)
+    sampled_checks(gpu_lib, w, (0.0, 0.0, 0.0), w.dt, nobs, 11, f"cube {N}^3")
+
+
+def test_sp4_film_sampled(gpu_lib):
+    """Full 500 x 125 x 3 film (padded 1024 x 256 x 8) under field 1, one
+    step at the paper's dt of 1e-13 s."""
+    w = workloads.SP4_500x125x3
+    h = workloads.field_mT(workloads.SP4_FIELD1_mT)
+    sampled_checks(gpu_lib, w, h, w.dt, 1024, 12, "SP4 500x125x3")
+
+
+@pytest.mark.parametrize("phase", ["relax", "field1", "field2"])
+def test_sp4_crop_trajectory(gpu_lib, phase):
+    """A 100 x 25 x 3 crop of the film, 100 steps at a stable dt: the S-state
+    relaxation phase (alpha = 0.5, no field, dt = 1e-14 s) and the reversal
+    phase (alpha = 0.02 at the fields of Sec. 4, dt = 2e-16 s)."""
+    base = workloads.SP4_500x125x3
+    if phase == "relax":
+        w = workloads.replace(base, n=(100, 25, 3), alpha=0.5, dt=1e-14)
+        h = np.zeros(3)
+    else:
+        w = workloads.replace(base, n=(100, 25, 3), dt=workloads.SP4_STABLE_DT)
+        h = workloads.field_mT(workloads.SP4_FIELD1_mT if phase == "field1" else workloads.SP4_FIELD2_mT)
+    m0, _ = workloads.inputs(w)
+    sim, P = make(gpu_lib, w, h)
+    m = gpu(m0)
+    mf = host(m)
+    sim.step(m, 100, w.dt)
+    sim.sync()
+    mo = P.run(mf, 100, w.dt)
+    e = rel(host(m), mo)
+    de = rel(host(m) - mf, mo - mf)
+    print(f"SP4 crop {phase}: 100 steps rel L2 {e:.2e}, of the change {de:.2e}")
+    assert e < 1e-4
+    assert de < 1e-3
+    sim.close()
