@@ -30,7 +30,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # (each scaled by what the same counter reads for a plain copy of known
 # size), keyed by kernel; valid only for the kernel sources whose SHA-256 is
 # recorded with them.  The summaries and commands are in profiles/.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    # k_zconv<64, false, 1>: FETCH_SIZE 76 681.4 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258100019,
+              "source_sha": "99a16077c62c821e6cdf4be3162a1acf51224fdd23cbffae6688c900421d403a"},
+}
 
 
 def kernel_source_sha():
@@ -303,7 +307,8 @@ def main():
     ap.add_argument("--compensated", action="store_true", help="time the compensated spectral multiply")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
-    ap.add_argument("--no-sweep", action="store_true", help="skip the N^3 cube size sweep and the SP4 film")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time the N^3 cube size sweep and the standard problem #4 film")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (3 times) for PMC counter calibration")
     args = ap.parse_args()
@@ -373,7 +378,7 @@ def main():
         bat = batch_rate(binding)
 
     sweep = sp4 = None
-    if not args.no_sweep:
+    if args.sweep:
         print("bench: N^3 cube size sweep", file=sys.stderr, flush=True)
         sweep = size_sweep(binding)
         print("bench: standard problem #4 film", file=sys.stderr, flush=True)

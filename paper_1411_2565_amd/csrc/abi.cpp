@@ -201,7 +201,8 @@ hipEvent_t take_event(mm_ctx *c)
     return e;
 }
 
-// run one launcher, bracketed by events when timing is on
+// run one single-kernel launcher; when timing is on, the kernel's dispatch
+// records a start and a stop event (its own execution interval)
 template <typename F>
 mm_status timed(mm_ctx *c, int kernel, const char *what, F &&launch)
 {
@@ -209,9 +210,16 @@ mm_status timed(mm_ctx *c, int kernel, const char *what, F &&launch)
     if (c->pending.size() >= 2048) MM_TRY(drain_timing(c));
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return fail(c, MM_EHIP, "hipEventCreate failed");
-    MM_TRY(hipcheck(c, hipEventRecord(a, c->stream), "event record"));
-    MM_TRY(hipcheck(c, launch(), what));
-    MM_TRY(hipcheck(c, hipEventRecord(b, c->stream), "event record"));
+    mmk::set_launch_events(a, b);
+    const hipError_t e = launch();
+    const bool used = !mmk::launch_events_pending();
+    mmk::clear_launch_events();
+    if (e != hipSuccess || !used) {
+        c->ev_free.push_back(a);
+        c->ev_free.push_back(b);
+        if (e == hipSuccess) return fail(c, MM_EHIP, "%s: timed launcher did not take the dispatch events", what);
+        return hipcheck(c, e, what);
+    }
     c->pending.push_back({kernel, a, b});
     return MM_OK;
 }

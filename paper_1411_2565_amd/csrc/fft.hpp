@@ -144,9 +144,11 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&l
                 // w^r from two table loads (w, w^2) and at most three complex
                 // products: table loads, not arithmetic, bound these passes
                 w[1] = twiddle<INV>(k, Ns * R);
-                if constexpr (R > 2) w[2] = twiddle<INV>(2 * k, Ns * R);
+                if constexpr (R > 2) {
+                    w[2] = twiddle<INV>(2 * k, Ns * R);
 #pragma unroll
-                for (int r = 3; r < R; ++r) w[r] = cmul(w[r - 2], w[2]);
+                    for (int r = 3; r < R; ++r) w[r] = cmul(w[r - 2], w[2]);
+                }
             }
 #pragma unroll
             for (int c = 0; c < NC; ++c) {

@@ -15,6 +15,8 @@
 //   xinv : inverse real FFT along x, keep nx: H_demag[3][nz][ny][nx]
 // The tensor spectrum already holds the factor -1/(Px Py Pz), so the last
 // inverse transform yields H_demag directly.
+#include <hip/hip_ext.h>
+
 #include "fft.hpp"
 #include "launch.hpp"
 
@@ -48,6 +50,19 @@ constexpr int kThreads = 256;
 // LDS budget (KB) of a z-pass block: sets its columns per block
 #ifndef MMK_ZC_LDS_KB
 #define MMK_ZC_LDS_KB 32
+#endif
+// Long z transforms: 8 points per thread from 256 points on, and from 128 on
+// a larger LDS budget with at most 16 columns (16 adjacent ky = one
+// 128-byte run per z row).  Measured on the 128^3 and 256^3 cubes: 2.6 ms
+// -> 1.9 ms per step at 256^3 against 4 points and the 32 KB budget.
+#ifndef MMK_ZC_E_LONG
+#define MMK_ZC_E_LONG 8
+#endif
+#ifndef MMK_ZC_LDS_KB_LONG
+#define MMK_ZC_LDS_KB_LONG 128
+#endif
+#ifndef MMK_ZC_CB_LONG
+#define MMK_ZC_CB_LONG 16
 #endif
 // lines per thread group in the y passes
 #ifndef MMK_Y_NC
@@ -92,9 +107,11 @@ struct YShape {
 // z pass: CB columns of the three components per block
 template <int L>
 struct ZShape {
-    static constexpr int E = L < MMK_ZC_E ? L : MMK_ZC_E, T = L / E;
-    static constexpr int CBmax = cmax(1, (MMK_ZC_LDS_KB * 1024) / (3 * 8 * lds_line(L)));
-    static constexpr int CB = cmin(cmax(1, 1024 / T), pow2floor(CBmax));
+    static constexpr int E0 = L >= 256 ? MMK_ZC_E_LONG : MMK_ZC_E;
+    static constexpr int E = L < E0 ? L : E0, T = L / E;
+    static constexpr int KB = L >= 128 ? MMK_ZC_LDS_KB_LONG : MMK_ZC_LDS_KB;
+    static constexpr int CBmax = cmax(1, (KB * 1024) / (3 * 8 * lds_line(L)));
+    static constexpr int CB = cmin(cmin(cmax(1, 1024 / T), pow2floor(CBmax)), L >= 128 ? MMK_ZC_CB_LONG : 1024);
     static constexpr int THREADS = T * CB;
     static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
 };
@@ -191,6 +208,17 @@ __global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Batch<XfwdDesc, NB>
     }
 }
 
+// S2 holds the y spectra as [c][kx][z][ky]: the z column of one (kx, ky)
+// has stride Py (one ky line) and a component spans nz Py-lines per kx, so
+// the z pass reads a compact address range per block.  S1 lines are
+// ordered (c, z, kx); this is the S2 line of S1 line `line`.
+__device__ __forceinline__ long long s2_line(long long line, const Geo &g)
+{
+    const long long kx = line % g.Hx, r = line / g.Hx;
+    const long long z = r % g.nz, c = r / g.nz;
+    return (c * g.Hx + kx) * g.nz + z;
+}
+
 // ------------------------------------------------------------------------
 // a2 / a4: FFT along y of contiguous columns (length Py, ny non-zeros in /
 // ny kept out), one column per T threads.
@@ -227,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
     for (int c = 0; c < NC; ++c) {
         const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
         if (line < nlines) {
-            float2 *out = S2 + line * L;
+            float2 *out = S2 + s2_line(line, g) * L;
 #pragma unroll
             for (int q = 0; q < E; ++q) out[t + q * T] = v[c][q];
         }
@@ -253,7 +281,7 @@ __global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
     for (int c = 0; c < NC; ++c) {
         const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
         const bool ok = line < nlines;
-        const float2 *in = S2 + line * L;
+        const float2 *in = S2 + s2_line(line, g) * L;
 #pragma unroll
         for (int q = 0; q < E; ++q) v[c][q] = ok ? in[t + q * T] : make_float2(0.f, 0.f);
         lds[c] = sm + (gi * NC + c) * lds_line(L);
@@ -332,15 +360,16 @@ __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B
     const int kx = blockIdx.y;
     const int ky = zc_tile(blockIdx.x, gridDim.x) * CB + col;
     const bool ok = ky < g.Py;
-    const long long plane = (long long)g.Hx * g.Py;  // stride between z planes
-    float2 *base = S2 + (long long)kx * g.Py + ky;
+    const long long zs = g.Py;                                // stride between z
+    const long long cs = (long long)g.Hx * g.nz * g.Py;       // between components
+    float2 *base = S2 + (long long)kx * g.nz * g.Py + ky;
     float2 v[3][E];
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int q = 0; q < E; ++q) {
             const int zz = t + q * T;
-            v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[((long long)c * g.nz + zz) * plane]
+            v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[c * cs + zz * zs]
                                                            : make_float2(0.f, 0.f);
         }
     float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
@@ -385,7 +414,7 @@ __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B
 #pragma unroll
             for (int q = 0; q < half_elems(E); ++q) {
                 const int zz = t + q * T;
-                if (zz < g.nz) base[((long long)c * g.nz + zz) * plane] = v[c][q];
+                if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
             }
     }
 }
@@ -1098,14 +1127,41 @@ static Extent extent(const Dsc *d, int count)
 }
 
 // one launch for 1 sample or up to kMaxBatch samples
+// Start/stop events for the next timed launch on this host thread.  The
+// dispatch records them itself (hipExtLaunchKernelGGL), so their interval is
+// the kernel's own execution, as a profiler's kernel trace reports it, without
+// the gaps that event records around the launch would add.
+static thread_local hipEvent_t t_ev_start = nullptr, t_ev_stop = nullptr;
+
+void set_launch_events(hipEvent_t start, hipEvent_t stop)
+{
+    t_ev_start = start;
+    t_ev_stop = stop;
+}
+
+bool launch_events_pending() { return t_ev_start != nullptr; }
+
+void clear_launch_events() { t_ev_start = t_ev_stop = nullptr; }
+
+#define MMK_LAUNCH(KERNEL, GRID, BLOCK, LDS, STREAM, ...)                                     \
+    do {                                                                                    \
+        if (t_ev_start) {                                                                   \
+            hipEvent_t a_ = t_ev_start, b_ = t_ev_stop;                                     \
+            t_ev_start = t_ev_stop = nullptr;                                               \
+            hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, a_, b_, 0, __VA_ARGS__); \
+        } else {                                                                            \
+            hipLaunchKernelGGL(KERNEL, GRID, BLOCK, LDS, STREAM, __VA_ARGS__);              \
+        }                                                                                   \
+    } while (0)
+
 #define MM_BATCH_LAUNCH(KERNEL, DESC, GRID, BLOCK, LDS, STREAM, ...)                           \
     do {                                                                                    \
         if (count == 1)                                                                     \
-            hipLaunchKernelGGL((KERNEL<__VA_ARGS__, 1>), GRID, BLOCK, LDS, STREAM,          \
-                               pack<DESC, 1>(d, count));                                    \
+            MMK_LAUNCH((KERNEL<__VA_ARGS__, 1>), GRID, BLOCK, LDS, STREAM,                  \
+                       pack<DESC, 1>(d, count));                                            \
         else                                                                                \
-            hipLaunchKernelGGL((KERNEL<__VA_ARGS__, kMaxBatch>), GRID, BLOCK, LDS, STREAM,  \
-                               pack<DESC, kMaxBatch>(d, count));                            \
+            MMK_LAUNCH((KERNEL<__VA_ARGS__, kMaxBatch>), GRID, BLOCK, LDS, STREAM,          \
+                       pack<DESC, kMaxBatch>(d, count));                                    \
     } while (0)
 
 hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s)
@@ -1217,10 +1273,10 @@ hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &
 #define LOCAL(MODE, V)                                                                        \
     do {                                                                                      \
         if (count == 1)                                                                       \
-            hipLaunchKernelGGL((k_local<MODE, V, 1>), grid, dim3(kThreads), 0, s,             \
+            MMK_LAUNCH((k_local<MODE, V, 1>), grid, dim3(kThreads), 0, s,             \
                                pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);     \
         else                                                                                  \
-            hipLaunchKernelGGL((k_local<MODE, V, kMaxBatch>), grid, dim3(kThreads), 0, s,     \
+            MMK_LAUNCH((k_local<MODE, V, kMaxBatch>), grid, dim3(kThreads), 0, s,     \
                                pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
     } while (0)
     if (mode == 0) {
@@ -1272,7 +1328,7 @@ hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, cons
                         float *g_hext, float *g_ms, hipStream_t s)
 {
     dim3 grid((unsigned)((g.N + kThreads - 1) / kThreads));
-    hipLaunchKernelGGL(k_adj_a, grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, lam1, dt, renorm, gH,
+    MMK_LAUNCH(k_adj_a, grid, dim3(kThreads), 0, s, g, p, m, Hd, ms_map, h_map, lam1, dt, renorm, gH,
                        lam_loc, g_hext, g_ms);
     return hipGetLastError();
 }
@@ -1281,7 +1337,7 @@ hipError_t launch_adj_b(const Geo &g, const LocalParams &p, const float *m, cons
                         const float *ms_map, const float *lam_loc, float *lam, float *g_ms, hipStream_t s)
 {
     dim3 grid((unsigned)((g.N + kThreads - 1) / kThreads));
-    hipLaunchKernelGGL(k_adj_b, grid, dim3(kThreads), 0, s, g, p, m, gH, D, ms_map, lam_loc, lam, g_ms);
+    MMK_LAUNCH(k_adj_b, grid, dim3(kThreads), 0, s, g, p, m, gH, D, ms_map, lam_loc, lam, g_ms);
     return hipGetLastError();
 }
 

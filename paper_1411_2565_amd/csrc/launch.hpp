@@ -85,6 +85,13 @@ hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s);
 hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &p, uint32_t terms, int mode,
                               float dt, int renorm, int *flag, hipStream_t s);
 
+// Timing: events that the next launch of a timed kernel on this host thread
+// records itself at dispatch start and end.  launch_events_pending() tells
+// whether they are still unused after a launcher returned.
+void set_launch_events(hipEvent_t start, hipEvent_t stop);
+bool launch_events_pending();
+void clear_launch_events();
+
 // single-sample forms
 hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s);
 hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s);
