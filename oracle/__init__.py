@@ -62,6 +62,8 @@ def lib():
         L.orc_llg_rhs.argtypes = [P, _D, _D, _D]
         L.orc_step.argtypes = [P, _D, ctypes.c_double, _D]
         L.orc_run.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, _D]
+        L.orc_run_rk.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_int]
+        L.orc_run_rk.restype = ctypes.c_int
         L.orc_energy.argtypes = [P, _D, _D]
         L.orc_adjoint.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, _D, _D, _D, _D]
         L.orc_adjoint.restype = ctypes.c_double
@@ -179,7 +181,19 @@ class Problem:
         lib().orc_llg_rhs(ctypes.byref(st), _p(m), _p(H), _p(f))
         return f
 
-    def run(self, m0, nsteps, dt, traj=False):
+    METHODS = {"euler": 0, "heun": 1, "rk4": 2}
+
+    def run(self, m0, nsteps, dt, traj=False, method="euler"):
+        """nsteps steps from m0: explicit Euler (Sec. 3), or Heun / classic
+        fourth-order Runge-Kutta with renormalised stage states."""
+        if method != "euler":
+            if traj:
+                raise ValueError("trajectories are stored for the Euler method only")
+            m = _f64(m0, self._shape()).copy()
+            st = self._struct()
+            if lib().orc_run_rk(ctypes.byref(st), _p(m), int(nsteps), float(dt), self.METHODS[method]):
+                raise ValueError(f"unknown method {method}")
+            return m
         m = _f64(m0, self._shape()).copy()
         st = self._struct()
         tr = np.zeros((nsteps + 1,) + self._shape()) if traj else None

@@ -536,6 +536,82 @@ void orc_run(const orc_problem *p, double *m, int64_t nsteps, double dt, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Explicit Runge-Kutta steps of the same right-hand side f (higher-order    */
+/* integrators are the paper's stated future work, Sec. 6).  With the        */
+/* Butcher tableau (A, b) of s stages:                                       */
+/*   m_1 = m,   m_i = P(m + dt sum_{j<i} A[i][j] k_j),   k_i = f(m_i, H(m_i))  */
+/*   m'  = P(m + dt sum_i b[i] k_i)                                          */
+/* P renormalises every cell when renorm is on, the identity otherwise: the  */
+/* stage states are unit vectors like the step result.                       */
+/*   method 1, Heun (explicit trapezoidal rule, order 2):                    */
+/*     A[1][0] = 1;  b = (1/2, 1/2)                                          */
+/*   method 2, classic fourth-order Runge-Kutta:                             */
+/*     A[1][0] = 1/2, A[2][1] = 1/2, A[3][2] = 1;  b = (1/6, 1/3, 1/3, 1/6)  */
+/*   method 0 is the Euler step above.                                       */
+/* ------------------------------------------------------------------------ */
+static void renormalise(const orc_problem *p, double *m, size_t N)
+{
+    if (!p->renorm) return;
+    for (size_t i = 0; i < N; ++i) {
+        const double n = sqrt(m[i] * m[i] + m[N + i] * m[N + i] + m[2 * N + i] * m[2 * N + i]);
+        m[i] /= n; m[N + i] /= n; m[2 * N + i] /= n;
+    }
+}
+
+int orc_step_rk(const orc_problem *p, double *m, double dt, int method)
+{
+    if (method == 0) {
+        orc_step(p, m, dt, NULL);
+        return 0;
+    }
+    double A[4][4] = {{0}}, b[4] = {0};
+    int s;
+    if (method == 1) {
+        s = 2;
+        A[1][0] = 1.0;
+        b[0] = 0.5; b[1] = 0.5;
+    } else if (method == 2) {
+        s = 4;
+        A[1][0] = 0.5; A[2][1] = 0.5; A[3][2] = 1.0;
+        b[0] = 1.0 / 6.0; b[1] = 1.0 / 3.0; b[2] = 1.0 / 3.0; b[3] = 1.0 / 6.0;
+    } else {
+        return -1;
+    }
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    double *k = (double *)malloc(sizeof(double) * 3 * N * s);
+    double *mi = (double *)malloc(sizeof(double) * 3 * N);
+    double *H = (double *)malloc(sizeof(double) * 3 * N);
+    for (int i = 0; i < s; ++i) {
+        for (size_t e = 0; e < 3 * N; ++e) {
+            double acc = 0.0;
+            for (int j = 0; j < i; ++j) acc += A[i][j] * k[(size_t)j * 3 * N + e];
+            mi[e] = m[e] + dt * acc;
+        }
+        if (i > 0) renormalise(p, mi, N);
+        orc_heff(p, mi, p->terms, H);
+        orc_llg_rhs(p, mi, H, k + (size_t)i * 3 * N);
+    }
+    for (size_t e = 0; e < 3 * N; ++e) {
+        double acc = 0.0;
+        for (int i = 0; i < s; ++i) acc += b[i] * k[(size_t)i * 3 * N + e];
+        m[e] += dt * acc;
+    }
+    renormalise(p, m, N);
+    free(k);
+    free(mi);
+    free(H);
+    return 0;
+}
+
+/* nsteps steps of the given method (0 Euler, 1 Heun, 2 RK4) from m, in place. */
+int orc_run_rk(const orc_problem *p, double *m, int64_t nsteps, double dt, int method)
+{
+    for (int64_t s = 0; s < nsteps; ++s)
+        if (orc_step_rk(p, m, dt, method)) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Energy of eq. (1) summed over cells (volume V = dx dy dz):                */
 /*   E_ex = A V sum_{neighbour pairs} |m_j - m_i|^2 / d^2                    */
 /*   E_d  = -(mu0 V / 2) sum Ms_i m_i . H_d,i                                */

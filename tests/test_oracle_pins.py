@@ -292,6 +292,58 @@ def test_macrospin_euler_converges_first_order():
         assert 1.8 < a / b < 2.2, errs
 
 
+@pytest.mark.parametrize("method,dts,ratio", [("heun", (4e-13, 2e-13, 1e-13), 4.0),
+                                              ("rk4", (2e-12, 1e-12, 5e-13), 16.0)])
+def test_macrospin_runge_kutta_orders(method, dts, ratio):
+    """Heun (order 2) and classic Runge-Kutta (order 4) on the exact
+    macrospin solution: the error falls by 2^order as dt halves."""
+    alpha, Hz, T = 0.1, 1e5, 0.2e-9
+    th0, ph0 = 1.0, 0.3
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)])
+    P = oracle.Problem((1, 1, 1), (5e-9,) * 3, alpha=alpha, hext=(0, 0, Hz), terms=oracle.T_ZEEMAN)
+    exact = macrospin(th0, ph0, Hz, alpha, 2.211e5, T)
+    errs = [np.linalg.norm(P.run(m0.reshape(3, 1, 1, 1), int(round(T / dt)), dt, method=method).ravel() - exact)
+            for dt in dts]
+    for a, b in zip(errs, errs[1:]):
+        assert 0.9 * ratio < a / b < 1.1 * ratio, errs
+
+
+def _coupled_problem():
+    rng = np.random.default_rng(3)
+    m = rng.standard_normal((3, 2, 3, 4))
+    m /= np.linalg.norm(m, axis=0)
+    P = oracle.Problem((4, 3, 2), (5e-9,) * 3, Ms=8e5, A=1.3e-11, Ku=3e4, u=(0.6, 0.0, 0.8), alpha=0.5,
+                       hext=(1e4, -2e4, 5e3))
+    return P, m
+
+
+@pytest.mark.parametrize("method,base,ratio", [("heun", 4e-14, 4.0), ("rk4", 8e-14, 16.0)])
+def test_runge_kutta_orders_with_all_terms(method, base, ratio):
+    """The same orders on a 4x3x2 sample with demag, exchange, anisotropy and
+    Zeeman terms (reference: the same method at dt/32).  A wrong tableau
+    entry would drop the order to one."""
+    P, m = _coupled_problem()
+    T = 4e-12
+    ref = P.run(m, int(round(T / (base / 32))), base / 32, method=method)
+    errs = [np.linalg.norm(P.run(m, int(round(T / dt)), dt, method=method) - ref)
+            for dt in (base, base / 2, base / 4)]
+    for a, b in zip(errs, errs[1:]):
+        assert 0.9 * ratio < a / b < 1.15 * ratio, errs
+
+
+def test_runge_kutta_methods_integrate_the_same_equation():
+    """Euler, Heun and RK4 at small steps reach the same state (they differ
+    only in truncation error), so the higher-order steps use the same f."""
+    P, m = _coupled_problem()
+    T = 4e-12
+    rk4 = P.run(m, 200, T / 200, method="rk4")
+    heun = P.run(m, 1600, T / 1600, method="heun")
+    euler = P.run(m, 12800, T / 12800)
+    scale = np.linalg.norm(rk4 - m)
+    assert np.linalg.norm(heun - rk4) < 1e-5 * scale
+    assert np.linalg.norm(euler - rk4) < 5e-3 * scale
+
+
 def test_norm_identity_without_renorm():
     """f is orthogonal to m, so |m + dt f|^2 = |m|^2 + dt^2 |f|^2 exactly."""
     n, d = (6, 5, 2), (5e-9,) * 3
