@@ -296,6 +296,25 @@ def sp4_rate(binding, steps=2048):
             "cell_steps_per_s": w.N * steps / min(te, tg)}
 
 
+def integrator_rates(binding, steps=200):
+    """Per-step time of the Euler, Heun and classic RK4 steps on the
+    256x256x32 block (1, 2 and 4 field evaluations per step), eager."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    w = workloads.BLOCK_256x256x32
+    m0, _ = workloads.inputs(w)
+    sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, device=0)
+    out = {"workload": "block 256x256x32, 5 nm cubes, dt=1e-13", "steps": steps}
+    for name, fl in (("euler", 0), ("heun", binding.MM_F_HEUN), ("rk4", binding.MM_F_RK4)):
+        m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+        sim.step(m, 10, w.dt, fl)
+        t = timed_steps(sim, m, steps, w.dt, fl)
+        out[name + "_us_per_step"] = round(1e6 * t / steps, 1)
+    sim.sync()
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -309,6 +328,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the N^3 cube size sweep and the standard problem #4 film")
+    ap.add_argument("--integrators", action="store_true",
+                    help="also time the Heun and RK4 steps on the block")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (3 times) for PMC counter calibration")
     args = ap.parse_args()
@@ -384,6 +405,11 @@ def main():
         print("bench: standard problem #4 film", file=sys.stderr, flush=True)
         sp4 = sp4_rate(binding)
 
+    rk = None
+    if args.integrators:
+        print("bench: Runge-Kutta steps", file=sys.stderr, flush=True)
+        rk = integrator_rates(binding)
+
     cpu = None
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
@@ -417,6 +443,7 @@ def main():
         "batch": bat,
         "size_sweep": sweep,
         "sp4": sp4,
+        "integrators": rk,
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:

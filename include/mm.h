@@ -78,7 +78,9 @@ enum { MM_T_EXCH = 1, MM_T_DEMAG = 2, MM_T_ANIS = 4, MM_T_ZEEMAN = 8, MM_T_ALL =
 enum {
     MM_F_NO_RENORM = 1,    /* skip m <- m/|m| after each Euler step */
     MM_F_COMPENSATED = 2,  /* compensated (Dot2) FP32 spectral tensor multiply */
-    MM_F_GRAPH = 4         /* mm_step_llg: replay captured chunks of 32 steps (needs a non-null stream) */
+    MM_F_GRAPH = 4,        /* mm_step_llg: replay captured chunks of 32 steps (needs a non-null stream) */
+    MM_F_HEUN = 8,         /* mm_step_llg: Heun step (explicit trapezoid, order 2) instead of Euler */
+    MM_F_RK4 = 16          /* mm_step_llg: classic fourth-order Runge-Kutta step instead of Euler */
 };
 
 /* Create a context for a geometry on HIP device `device`; work is enqueued
@@ -146,7 +148,16 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m_dev, float *h_dev, uint32_t 
  * chunk of 32 steps (or the largest even count below nsteps), captured on
  * the first such call for this (m_dev, dt, flags, stream) and kept until a
  * setter changes what the kernels read; results are identical to the eager
- * path.  The capture requires a non-null stream. */
+ * path.  The capture requires a non-null stream.
+ * MM_F_HEUN or MM_F_RK4 (not both) replaces each Euler step by an explicit
+ * Runge-Kutta step of the same right-hand side f (higher-order integrators
+ * are the paper's future work, Sec. 6): stages k_i = f(m_i) with
+ * m_1 = m and m_{i+1} = P(m + dt a_i k_i), result P(m + dt sum_i b_i k_i),
+ * P the renormalisation (identity under MM_F_NO_RENORM).  Heun: a = (1),
+ * b = (1/2, 1/2), two field evaluations per step; classic RK4:
+ * a = (1/2, 1/2, 1), b = (1/6, 1/3, 1/3, 1/6), four.  Not accepted by
+ * mm_forward_store, mm_adjoint_step or the batch calls (MM_EUNSUP): the
+ * adjoint is that of the Euler step. */
 mm_status mm_step_llg(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32_t flags);
 
 /* FP64 reductions of the energy of eq. (1) summed over cells and of the

@@ -51,7 +51,7 @@ struct mm_ctx {
     char *ws = nullptr;
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
-    size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_T = 0, o_tA = 0, o_tB = 0;
+    size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_rk = 0, o_T = 0, o_tA = 0, o_tB = 0;
     size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
     std::string err;
@@ -163,6 +163,7 @@ void layout(mm_ctx *c)
     c->o_S1 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.ny);
     c->o_S2 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.Py);
     c->o_mtmp = st.take(sizeof(float) * 3 * N);
+    c->o_rk = st.take(sizeof(float) * 9 * N);  // Runge-Kutta: two stage states + accumulator
     Carve tb;
     tb.off = region;
     c->o_T = tb.take(sizeof(double) * 6 * N);
@@ -282,7 +283,9 @@ mm_status check_step_args(mm_ctx *c, const float *m, int64_t nsteps, double dt, 
     if (!m || !aligned16(m)) return fail(c, MM_EINVAL, "m must be a 16-byte aligned device pointer");
     if (nsteps < 0) return fail(c, MM_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0) || !std::isfinite(dt)) return fail(c, MM_EINVAL, "dt must be finite and > 0");
-    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED)) return fail(c, MM_EINVAL, "unknown flag bits 0x%x", flags);
+    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_HEUN | MM_F_RK4))
+        return fail(c, MM_EINVAL, "unknown flag bits 0x%x", flags);
+    if ((flags & MM_F_HEUN) && (flags & MM_F_RK4)) return fail(c, MM_EINVAL, "MM_F_HEUN and MM_F_RK4 together");
     MM_TRY(need_ws(c));
     if (!c->have_mat) return fail(c, MM_ESTATE, "material not set");
     if (!c->tensor) return fail(c, MM_ESTATE, "mm_build_tensor has not been called");
@@ -490,10 +493,42 @@ namespace {
 template <class Src, class Dst, class HdOut>
 mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src src, Dst dst, HdOut hd)
 {
-    const mmk::LocalParams p = local_params(c);
+    mmk::LocalParams p = local_params(c);
     const bool comp = flags & MM_F_COMPENSATED;
     const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
     int *flag = c->at<int>(c->o_flag);
+    if (flags & (MM_F_HEUN | MM_F_RK4)) {
+        // explicit Runge-Kutta with a_{i+1} = A[i+1][i] the only nonzero
+        // entry of each row (true of Heun and classic RK4): stage i reads
+        // state i, writes state i+1 from m_base and its own k_i
+        const bool heun = flags & MM_F_HEUN;
+        const int ns = heun ? 2 : 4;
+        static const float a_heun[2] = {1.f, 0.f}, b_heun[2] = {0.5f, 0.5f};
+        static const float a_rk4[4] = {0.5f, 0.5f, 1.f, 0.f};
+        static const float b_rk4[4] = {1.f / 6.f, 1.f / 3.f, 1.f / 3.f, 1.f / 6.f};
+        const size_t S = 3 * (size_t)c->g.N;
+        float *stage[2] = {c->at<float>(c->o_rk), c->at<float>(c->o_rk) + S};
+        float *acc = c->at<float>(c->o_rk) + 2 * S;
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const float *base = src(s);
+            const float *eval = base;
+            for (int i = 0; i < ns; ++i) {
+                float *Hd = nullptr;
+                MM_TRY(demag(c, eval, comp, &Hd, hd(s)));
+                p.stage_a = heun ? a_heun[i] : a_rk4[i];
+                p.stage_b = heun ? b_heun[i] : b_rk4[i];
+                p.stage_first = i == 0;
+                p.stage_last = i == ns - 1;
+                float *out = p.stage_last ? dst(s) : stage[i & 1];
+                MM_TRY(timed(c, MM_K_LOCAL, "runge-kutta stage", [&] {
+                    return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, (float)dt,
+                                             renorm, out, flag, c->stream);
+                }));
+                eval = out;
+            }
+        }
+        return MM_OK;
+    }
     for (int64_t s = 0; s < nsteps; ++s) {
         float *Hd = nullptr;
         MM_TRY(demag(c, src(s), comp, &Hd, hd(s)));
@@ -585,6 +620,8 @@ mm_status mm_forward_store(mm_ctx *c, float *m, int64_t nsteps, double dt, uint3
 {
     if (!c) return MM_EINVAL;
     MM_TRY(check_step_args(c, m, nsteps, dt, flags));
+    if (flags & (MM_F_HEUN | MM_F_RK4))
+        return fail(c, MM_EUNSUP, "the stored replay and the adjoint cover the Euler step only");
     if (nsteps > 0 && (!m_traj || !hd_traj || !aligned16(m_traj) || !aligned16(hd_traj)))
         return fail(c, MM_EINVAL, "trajectory buffers must be 16-byte aligned device pointers");
     MM_TRY(set_device(c));
@@ -604,6 +641,7 @@ mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float 
 {
     if (!c) return MM_EINVAL;
     MM_TRY(check_step_args(c, m_n, 1, dt, flags));
+    if (flags & (MM_F_HEUN | MM_F_RK4)) return fail(c, MM_EUNSUP, "the adjoint covers the Euler step only");
     if (!hd_n || !lam || !aligned16(hd_n) || !aligned16(lam))
         return fail(c, MM_EINVAL, "hd_n and lam must be 16-byte aligned device pointers");
     if ((g_hext && !aligned16(g_hext)) || (g_ms && !aligned16(g_ms)))
@@ -1045,6 +1083,7 @@ mm_status mm_batch_step(mm_batch *b, float *m, int64_t nsteps, double dt, uint32
     if (!m || !aligned16(m)) return bfail(b, MM_EINVAL, "m must be a 16-byte aligned device pointer");
     if (nsteps < 0) return bfail(b, MM_EINVAL, "nsteps must be >= 0");
     if (!(dt > 0) || !std::isfinite(dt)) return bfail(b, MM_EINVAL, "dt must be finite and > 0");
+    if (flags & (MM_F_HEUN | MM_F_RK4)) return bfail(b, MM_EUNSUP, "batched steps are Euler steps only");
     if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_GRAPH))
         return bfail(b, MM_EINVAL, "unknown flag bits 0x%x", flags);
     if (!b->ws) return bfail(b, MM_ESTATE, "no workspace set");

@@ -641,6 +641,63 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
         for (int c = 0; c < 3; ++c) vstore<V>(out_h + c * N + i0, h[c]);
         return;
     }
+    if (MODE == 2) {
+        // one explicit Runge-Kutta stage (coefficients in p; the stage
+        // states, like the step result, are renormalised unless renorm = 0)
+        float base[3][V], acc[3][V];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vload<V>(D.m_base + c * N + i0, base[c]);
+            if (p.stage_first) {
+#pragma unroll
+                for (int j = 0; j < V; ++j) acc[c][j] = base[c][j];
+            } else {
+                vload<V>(D.acc + c * N + i0, acc[c]);
+            }
+        }
+        const float wb = p.stage_b * dt, wa = p.stage_a * dt;
+        float o[3][V];
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
+            const float hx = h[0][j], hy = h[1][j], hz = h[2][j];
+            const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
+            const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
+            const float kx = p.c1 * ax + p.c2 * bx, ky = p.c1 * ay + p.c2 * by, kz = p.c1 * az + p.c2 * bz;
+            acc[0][j] = fmaf(wb, kx, acc[0][j]);
+            acc[1][j] = fmaf(wb, ky, acc[1][j]);
+            acc[2][j] = fmaf(wb, kz, acc[2][j]);
+            float nx_, ny_, nz_;
+            if (p.stage_last) {
+                nx_ = acc[0][j];
+                ny_ = acc[1][j];
+                nz_ = acc[2][j];
+            } else {
+                nx_ = fmaf(wa, kx, base[0][j]);
+                ny_ = fmaf(wa, ky, base[1][j]);
+                nz_ = fmaf(wa, kz, base[2][j]);
+            }
+            if (renorm) {
+                const float sc = rsqrtf(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+                nx_ *= sc;
+                ny_ *= sc;
+                nz_ *= sc;
+            }
+            bad |= !(isfinite(nx_) && isfinite(ny_) && isfinite(nz_));
+            o[0][j] = nx_;
+            o[1][j] = ny_;
+            o[2][j] = nz_;
+        }
+        if (bad) *flag = 1;
+        if (!p.stage_last) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vstore<V>(D.acc + c * N + i0, acc[c]);
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vstore<V>(out_m + c * N + i0, o[c]);
+        return;
+    }
     float o[3][V];
     bool bad = false;
 #pragma unroll
@@ -1281,8 +1338,10 @@ hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &
     } while (0)
     if (mode == 0) {
         if (vec) LOCAL(0, 4); else LOCAL(0, 1);
-    } else {
+    } else if (mode == 1) {
         if (vec) LOCAL(1, 4); else LOCAL(1, 1);
+    } else {
+        if (vec) LOCAL(2, 4); else LOCAL(2, 1);
     }
 #undef LOCAL
     return hipGetLastError();
@@ -1321,6 +1380,14 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
 {
     LocalDesc d{g, m, Hd, ms_map, h_map, out_m, out_h, p.h0, p.h1, p.h2};
     return launch_local_batch(&d, 1, p, terms, mode, dt, renorm, flag, s);
+}
+
+hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
+                        const float *h_map, const float *m_base, float *acc, float dt, int renorm, float *out_m,
+                        int *flag, hipStream_t s)
+{
+    LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc};
+    return launch_local_batch(&d, 1, p, 15u, 2, dt, renorm, flag, s);
 }
 
 hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,

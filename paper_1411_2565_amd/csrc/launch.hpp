@@ -22,6 +22,11 @@ struct LocalParams {
     float u0, u1, u2;    // easy axis
     float h0, h1, h2;    // uniform external field (A/m)
     float c1, c2;        // LLG: f = c1 m x H + c2 m x (m x H)
+    // mode 2, one Runge-Kutta stage with k = f(m, H(m)) at this stage's state:
+    //   acc' = (first ? m_base : acc) + stage_b dt k
+    //   last: m_out = P(acc');  else: acc = acc', m_out = P(m_base + stage_a dt k)
+    float stage_a, stage_b;
+    int stage_first, stage_last;
 };
 
 // Per-sample arguments of one pass.  A launch processes up to kMaxBatch
@@ -53,9 +58,11 @@ struct XinvDesc {
 struct LocalDesc {
     Geo g;
     const float *m, *Hd, *ms_map, *h_map;
-    float *m_out;  // Euler step output (mode 1)
+    float *m_out;  // Euler step output (mode 1), next stage state or step result (mode 2)
     float *h_out;  // field output (mode 0)
     float h0, h1, h2;  // uniform external field of this sample
+    const float *m_base;  // mode 2: state at the start of the step
+    float *acc;           // mode 2: m_base + dt sum_j b_j k_j so far (3N floats)
 };
 template <typename D, int NB>
 struct Batch {
@@ -103,6 +110,11 @@ hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
 hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
                         const float *ms_map, const float *h_map, uint32_t terms, int mode,
                         float dt, int renorm, float *out_m, float *out_h, int *flag, hipStream_t s);
+// one Runge-Kutta stage (all field terms; coefficients in p.stage_*): reads
+// m (the stage state), Hd = H_demag(m), m_base and acc; writes out_m and acc
+hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
+                        const float *h_map, const float *m_base, float *acc, float dt, int renorm, float *out_m,
+                        int *flag, hipStream_t s);
 
 // adjoint of one Euler step: local part (a) and the non-local completion (b)
 hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
