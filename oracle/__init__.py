@@ -64,6 +64,9 @@ def lib():
         L.orc_run.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, _D]
         L.orc_run_rk.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, ctypes.c_int]
         L.orc_run_rk.restype = ctypes.c_int
+        L.orc_run_adaptive.argtypes = [P, _D, ctypes.c_double, _D, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_int64, _I64, _I64]
+        L.orc_run_adaptive.restype = ctypes.c_int
         L.orc_energy.argtypes = [P, _D, _D]
         L.orc_adjoint.argtypes = [P, _D, ctypes.c_int64, ctypes.c_double, _D, _D, _D, _D]
         L.orc_adjoint.restype = ctypes.c_double
@@ -200,6 +203,21 @@ class Problem:
         lib().orc_run(ctypes.byref(st), _p(m), int(nsteps), float(dt),
                       _p(tr) if traj else ctypes.cast(None, _D))
         return (m, tr) if traj else m
+
+    PAIRS = {"heun_euler": 1, "bs23": 2}
+
+    def run_adaptive(self, m0, t_end, dt0, tol, pair="heun_euler", max_steps=10**6):
+        """Adaptive steps with an embedded pair up to time t_end: returns
+        (m, last proposed dt, accepted steps, rejected steps)."""
+        m = _f64(m0, self._shape()).copy()
+        st = self._struct()
+        dt = ctypes.c_double(float(dt0))
+        acc, rej = ctypes.c_int64(0), ctypes.c_int64(0)
+        rc = lib().orc_run_adaptive(ctypes.byref(st), _p(m), float(t_end), ctypes.byref(dt), float(tol),
+                                    self.PAIRS[pair], int(max_steps), ctypes.byref(acc), ctypes.byref(rej))
+        if rc:
+            raise RuntimeError(f"orc_run_adaptive failed ({rc})")
+        return m, dt.value, acc.value, rej.value
 
     def step_cells(self, m, cells, dt):
         """One Euler step evaluated only at the given linear cell indices

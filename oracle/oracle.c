@@ -612,6 +612,107 @@ int orc_run_rk(const orc_problem *p, double *m, int64_t nsteps, double dt, int m
 }
 
 /* ------------------------------------------------------------------------ */
+/* Adaptive time steps (named as future work in Sec. 6) with an embedded     */
+/* Runge-Kutta pair: the step advances with the higher-order result          */
+/*   m' = P(m + dt sum_i b[i] k_i)                                           */
+/* and estimates its local error from the lower-order one,                    */
+/*   err = max over cells of | dt sum_i (b[i] - bh[i]) k_i |                  */
+/* (unprojected sums; for pair 2 the last k is f at m', so b has 0 there).   */
+/* A step is accepted when err <= tol.  Accepted or not, the next step is    */
+/*   dt <- dt min(5, max(0.2, 0.9 (tol/err)^(1/(q+1))))   (5 when err = 0),  */
+/* q the order of the lower method, and the step that would pass t_end is    */
+/* shortened to end there.                                                   */
+/*   pair 1, Heun with embedded Euler, order 2(1):                           */
+/*     A[1][0] = 1;  b = (1/2, 1/2);  bh = (1, 0)                            */
+/*   pair 2, Bogacki-Shampine, order 3(2):                                   */
+/*     A[1][0] = 1/2, A[2][1] = 3/4;  b = (2/9, 1/3, 4/9, 0);                */
+/*     bh = (7/24, 1/4, 1/3, 1/8), the fourth stage evaluated at m'          */
+/* Returns 0, or -1 for an unknown pair, -2 when max_steps attempts do not   */
+/* reach t_end.                                                              */
+/* ------------------------------------------------------------------------ */
+int orc_run_adaptive(const orc_problem *p, double *m, double t_end, double *dt_io, double tol, int pair,
+                     int64_t max_steps, int64_t *accepted, int64_t *rejected)
+{
+    double A[4][4] = {{0}}, b[4] = {0}, bh[4] = {0};
+    int s, q;
+    if (pair == 1) {
+        s = 2; q = 1;
+        A[1][0] = 1.0;
+        b[0] = 0.5; b[1] = 0.5;
+        bh[0] = 1.0;
+    } else if (pair == 2) {
+        s = 4; q = 2;
+        A[1][0] = 0.5; A[2][1] = 0.75;
+        b[0] = 2.0 / 9.0; b[1] = 1.0 / 3.0; b[2] = 4.0 / 9.0;
+        bh[0] = 7.0 / 24.0; bh[1] = 0.25; bh[2] = 1.0 / 3.0; bh[3] = 0.125;
+    } else {
+        return -1;
+    }
+    /* pair 2: stages 0-2 build m', stage 3 is f(m') */
+    const int sres = pair == 2 ? 3 : s;
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    double *k = (double *)malloc(sizeof(double) * 3 * N * s);
+    double *mi = (double *)malloc(sizeof(double) * 3 * N);
+    double *mn = (double *)malloc(sizeof(double) * 3 * N);
+    double *H = (double *)malloc(sizeof(double) * 3 * N);
+    double t = 0.0, dt = *dt_io;
+    int64_t acc = 0, rej = 0;
+    int status = 0;
+    while (t < t_end) {
+        if (acc + rej >= max_steps) { status = -2; break; }
+        const double h = (t + dt > t_end) ? t_end - t : dt;
+        for (int i = 0; i < sres; ++i) {
+            for (size_t e = 0; e < 3 * N; ++e) {
+                double a = 0.0;
+                for (int j = 0; j < i; ++j) a += A[i][j] * k[(size_t)j * 3 * N + e];
+                mi[e] = m[e] + h * a;
+            }
+            if (i > 0) renormalise(p, mi, N);
+            orc_heff(p, mi, p->terms, H);
+            orc_llg_rhs(p, mi, H, k + (size_t)i * 3 * N);
+        }
+        for (size_t e = 0; e < 3 * N; ++e) {
+            double a = 0.0;
+            for (int i = 0; i < sres; ++i) a += b[i] * k[(size_t)i * 3 * N + e];
+            mn[e] = m[e] + h * a;
+        }
+        renormalise(p, mn, N);
+        if (pair == 2) {
+            orc_heff(p, mn, p->terms, H);
+            orc_llg_rhs(p, mn, H, k + (size_t)3 * 3 * N);
+        }
+        double err = 0.0;
+        for (size_t i = 0; i < N; ++i) {
+            double e2 = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                double a = 0.0;
+                for (int j = 0; j < s; ++j) a += (b[j] - bh[j]) * k[(size_t)j * 3 * N + c * N + i];
+                e2 += (h * a) * (h * a);
+            }
+            const double e = sqrt(e2);
+            if (!(e <= err)) err = e;  /* NaN propagates */
+        }
+        if (err != err) { status = -3; break; }
+        if (err <= tol) {
+            memcpy(m, mn, sizeof(double) * 3 * N);
+            t += h;
+            ++acc;
+        } else {
+            ++rej;
+        }
+        double f = err > 0.0 ? 0.9 * pow(tol / err, 1.0 / (q + 1)) : 5.0;
+        if (f > 5.0) f = 5.0;
+        if (f < 0.2) f = 0.2;
+        dt = h * f;
+    }
+    *dt_io = dt;
+    if (accepted) *accepted = acc;
+    if (rejected) *rejected = rej;
+    free(k); free(mi); free(mn); free(H);
+    return status;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Energy of eq. (1) summed over cells (volume V = dx dy dz):                */
 /*   E_ex = A V sum_{neighbour pairs} |m_j - m_i|^2 / d^2                    */
 /*   E_d  = -(mu0 V / 2) sum Ms_i m_i . H_d,i                                */

@@ -344,6 +344,50 @@ def test_runge_kutta_methods_integrate_the_same_equation():
     assert np.linalg.norm(euler - rk4) < 5e-3 * scale
 
 
+def _macrospin_setup():
+    alpha, Hz, T = 0.1, 1e5, 0.2e-9
+    th0, ph0 = 1.0, 0.3
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(3, 1, 1, 1)
+    P = oracle.Problem((1, 1, 1), (5e-9,) * 3, alpha=alpha, hext=(0, 0, Hz), terms=oracle.T_ZEEMAN)
+    return P, m0, T, macrospin(th0, ph0, Hz, alpha, 2.211e5, T)
+
+
+@pytest.mark.parametrize("pair,steps_ratio", [("heun_euler", 10.0), ("bs23", 100.0 ** (1 / 3))])
+def test_adaptive_pairs_scale_with_tolerance(pair, steps_ratio):
+    """Adaptive steps on the exact macrospin solution: the global error is
+    proportional to the tolerance, and the number of accepted steps grows as
+    tol^(-1/(q+1)) (q the lower order: 1 for Heun/Euler, 2 for
+    Bogacki-Shampine).  A wrong weight in either member of the pair changes
+    one of the two exponents."""
+    P, m0, T, exact = _macrospin_setup()
+    res = {tol: P.run_adaptive(m0, T, 1e-13, tol, pair) for tol in (1e-5, 1e-7)}
+    err = {tol: np.linalg.norm(r[0].ravel() - exact) for tol, r in res.items()}
+    assert 70 < err[1e-5] / err[1e-7] < 140, err
+    assert err[1e-7] < 1e-6
+    ratio = res[1e-7][2] / res[1e-5][2]
+    assert 0.8 * steps_ratio < ratio < 1.25 * steps_ratio, (res[1e-5][2], res[1e-7][2])
+
+
+def test_heun_euler_estimate_is_the_difference_of_the_two_steps():
+    """Without renormalisation the error estimate of the 2(1) pair after one
+    step equals max over cells |Heun step - Euler step|, computed here from
+    the oracle's separate Euler and Heun steps; it is read back from the
+    proposed next step dt' = dt 0.9 (tol/err)^(1/2)."""
+    rng = np.random.default_rng(12)
+    m = rng.standard_normal((3, 2, 3, 4))
+    m /= np.linalg.norm(m, axis=0)
+    P = oracle.Problem((4, 3, 2), (5e-9,) * 3, Ms=8e5, A=1.3e-11, alpha=0.3, hext=(1e4, 0, 0), renorm=False)
+    dt = 2e-14
+    diff = P.run(m, 1, dt, method="heun") - P.run(m, 1, dt)
+    err = np.linalg.norm(diff, axis=0).max()
+    tol = 2.0 * err
+    m1, dt_next, acc, rej = P.run_adaptive(m, dt, dt, tol, "heun_euler")
+    assert (acc, rej) == (1, 0)
+    np.testing.assert_allclose(m1, P.run(m, 1, dt, method="heun"), rtol=0, atol=1e-15)
+    implied = tol * (0.9 * dt / dt_next) ** 2
+    np.testing.assert_allclose(implied, err, rtol=1e-9)
+
+
 def test_norm_identity_without_renorm():
     """f is orthogonal to m, so |m + dt f|^2 = |m|^2 + dt^2 |f|^2 exactly."""
     n, d = (6, 5, 2), (5e-9,) * 3
