@@ -80,7 +80,8 @@ enum {
     MM_F_COMPENSATED = 2,  /* compensated (Dot2) FP32 spectral tensor multiply */
     MM_F_GRAPH = 4,        /* mm_step_llg: replay captured chunks of 32 steps (needs a non-null stream) */
     MM_F_HEUN = 8,         /* mm_step_llg: Heun step (explicit trapezoid, order 2) instead of Euler */
-    MM_F_RK4 = 16          /* mm_step_llg: classic fourth-order Runge-Kutta step instead of Euler */
+    MM_F_RK4 = 16,         /* mm_step_llg: classic fourth-order Runge-Kutta step instead of Euler */
+    MM_F_BS23 = 32         /* mm_step_adaptive: Bogacki-Shampine 3(2) pair (MM_F_HEUN: Heun/Euler 2(1)) */
 };
 
 /* Create a context for a geometry on HIP device `device`; work is enqueued
@@ -150,8 +151,8 @@ mm_status mm_compute_heff(mm_ctx *c, const float *m_dev, float *h_dev, uint32_t 
  * setter changes what the kernels read; results are identical to the eager
  * path.  The capture requires a non-null stream.
  * MM_F_HEUN or MM_F_RK4 (not both) replaces each Euler step by an explicit
- * Runge-Kutta step of the same right-hand side f (higher-order integrators
- * are the paper's future work, Sec. 6): stages k_i = f(m_i) with
+ * Runge-Kutta step of the same right-hand side f (fixed-step counterparts
+ * of the adaptive steps below, Sec. 6): stages k_i = f(m_i) with
  * m_1 = m and m_{i+1} = P(m + dt a_i k_i), result P(m + dt sum_i b_i k_i),
  * P the renormalisation (identity under MM_F_NO_RENORM).  Heun: a = (1),
  * b = (1/2, 1/2), two field evaluations per step; classic RK4:
@@ -174,6 +175,30 @@ mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
  * demag evaluation of this context (mm_compute_heff, mm_reduce, steps and
  * adjoint steps), in addition to per-call MM_F_COMPENSATED. */
 mm_status mm_set_compensated(mm_ctx *c, int on);
+
+/* Adaptive time steps (named as future work in Sec. 6): advance m_dev in
+ * place from t = 0 to t_end (s) with an embedded explicit Runge-Kutta pair
+ * of the right-hand side of eq. (3), selected by exactly one of
+ *   MM_F_HEUN  Heun with embedded Euler, order 2(1): b = (1/2, 1/2),
+ *              bh = (1, 0);
+ *   MM_F_BS23  Bogacki-Shampine 3(2): a = (1/2, 3/4), b = (2/9, 1/3, 4/9),
+ *              a fourth stage at the new state, bh = (7/24, 1/4, 1/3, 1/8);
+ * plus optionally MM_F_NO_RENORM and MM_F_COMPENSATED.  Stage states and the
+ * result are renormalised as in mm_step_llg.  Each attempt with step h
+ * estimates err = max over cells |h sum_i (b_i - bh_i) k_i| (FP32, reduced
+ * on the GPU) and is accepted when err <= tol (tol dimensionless, in units
+ * of |m|).  Either way the next step is
+ *   h * min(5, max(0.2, 0.9 (tol/err)^(1/(q+1))))   (q = 1 or 2; 5 if err = 0)
+ * and a step that would pass t_end is shortened to end there.  *dt_io gives
+ * the first step and receives the last proposed one; *accepted / *rejected
+ * (may be NULL) count the attempts.  The host waits for the GPU after every
+ * attempt (the decision needs the error), so this call is synchronous and is
+ * not for graph capture.  Errors: MM_EINVAL for bad arguments or flags;
+ * MM_ESTATE after max_steps attempts without reaching t_end, and
+ * MM_ENONFINITE for a non-finite estimate; in both cases m_dev holds the last
+ * accepted state. */
+mm_status mm_step_adaptive(mm_ctx *c, float *m_dev, double t_end, double *dt_io, double tol, uint32_t flags,
+                           int64_t max_steps, int64_t *accepted, int64_t *rejected);
 
 /* Forward rollout that keeps what the adjoint needs: advances m_dev in place
  * by nsteps Euler steps exactly as mm_step_llg does, and stores the state

@@ -536,9 +536,10 @@ void orc_run(const orc_problem *p, double *m, int64_t nsteps, double dt, double 
 }
 
 /* ------------------------------------------------------------------------ */
-/* Explicit Runge-Kutta steps of the same right-hand side f (higher-order    */
-/* integrators are the paper's stated future work, Sec. 6).  With the        */
-/* Butcher tableau (A, b) of s stages:                                       */
+/* Explicit Runge-Kutta steps of the same right-hand side f (fixed-step     */
+/* members of the Runge-Kutta family that adaptive time steps, named as      */
+/* future work in Sec. 6, build on).  With the Butcher tableau (A, b) of s   */
+/* stages:                                                                   */
 /*   m_1 = m,   m_i = P(m + dt sum_{j<i} A[i][j] k_j),   k_i = f(m_i, H(m_i))  */
 /*   m'  = P(m + dt sum_i b[i] k_i)                                          */
 /* P renormalises every cell when renorm is on, the identity otherwise: the  */

@@ -15,7 +15,7 @@ from . import build as _build
 
 MM_OK, MM_EINVAL, MM_ESTATE, MM_ENOMEM, MM_EHIP, MM_EUNSUP, MM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MM_T_EXCH, MM_T_DEMAG, MM_T_ANIS, MM_T_ZEEMAN, MM_T_ALL = 1, 2, 4, 8, 15
-MM_F_NO_RENORM, MM_F_COMPENSATED, MM_F_GRAPH, MM_F_HEUN, MM_F_RK4 = 1, 2, 4, 8, 16
+MM_F_NO_RENORM, MM_F_COMPENSATED, MM_F_GRAPH, MM_F_HEUN, MM_F_RK4, MM_F_BS23 = 1, 2, 4, 8, 16, 32
 
 _NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ESTATE", -3: "MM_ENOMEM", -4: "MM_EHIP",
           -5: "MM_EUNSUP", -6: "MM_ENONFINITE"}
@@ -69,6 +69,9 @@ def load():
         "mm_sync": [_P],
         "mm_kernel_timing": [_P, ctypes.c_int],
         "mm_set_compensated": [_P, ctypes.c_int],
+        "mm_step_adaptive": [_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                             ctypes.c_uint32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                             ctypes.POINTER(ctypes.c_int64)],
         "mm_forward_store": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32, _P, _P],
         "mm_adjoint_step": [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_uint32],
         "mm_kernel_times": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
@@ -208,6 +211,17 @@ def mm_sync(ctx):
 
 def mm_set_compensated(ctx, on):
     _check(ctx, load().mm_set_compensated(ctx, int(bool(on))), "mm_set_compensated")
+
+
+def mm_step_adaptive(ctx, m, t_end, dt, tol, flags, max_steps, N):
+    """Returns (last proposed dt, accepted attempts, rejected attempts)."""
+    import torch
+    d = ctypes.c_double(float(dt))
+    a, r = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(ctx, load().mm_step_adaptive(ctx, _dev(m, torch.float32, 3 * N, "m"), float(t_end), ctypes.byref(d),
+                                        float(tol), int(flags), int(max_steps), ctypes.byref(a), ctypes.byref(r)),
+           "mm_step_adaptive")
+    return d.value, a.value, r.value
 
 
 def mm_forward_store(ctx, m, nsteps, dt, flags, m_traj, hd_traj, N):
@@ -412,6 +426,11 @@ class Sim:
         self._s()
         mm_step_llg(self.ctx, m, nsteps, dt, flags, self.N)
         return m
+
+    def run_adaptive(self, m, t_end, dt0, tol, flags=MM_F_HEUN, max_steps=10**7):
+        """Adaptive steps of m (in place) up to t_end: (dt, accepted, rejected)."""
+        self._s()
+        return mm_step_adaptive(self.ctx, m, t_end, dt0, tol, flags, max_steps, self.N)
 
     def reduce(self, m):
         import torch

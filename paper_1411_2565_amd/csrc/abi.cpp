@@ -163,7 +163,7 @@ void layout(mm_ctx *c)
     c->o_S1 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.ny);
     c->o_S2 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.Py);
     c->o_mtmp = st.take(sizeof(float) * 3 * N);
-    c->o_rk = st.take(sizeof(float) * 9 * N);  // Runge-Kutta: two stage states + accumulator
+    c->o_rk = st.take(sizeof(float) * 12 * N);  // Runge-Kutta: two stage states, accumulator, error accumulator
     Carve tb;
     tb.off = region;
     c->o_T = tb.take(sizeof(double) * 6 * N);
@@ -521,8 +521,8 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
                 p.stage_last = i == ns - 1;
                 float *out = p.stage_last ? dst(s) : stage[i & 1];
                 MM_TRY(timed(c, MM_K_LOCAL, "runge-kutta stage", [&] {
-                    return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, (float)dt,
-                                             renorm, out, flag, c->stream);
+                    return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, nullptr,
+                                             (float)dt, renorm, out, flag, c->stream);
                 }));
                 eval = out;
             }
@@ -537,6 +537,58 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
                                      renorm, dst(s), nullptr, flag, c->stream);
         }));
     }
+    return MM_OK;
+}
+
+// One attempted step of an embedded pair from `base` to `out` with step h;
+// the stream is synchronised and *err receives max over cells of the local
+// error estimate |dt sum_i (b_i - bh_i) k_i|.
+//   2(1) Heun / Euler:      a = (1), b = (1/2, 1/2), bh = (1, 0)
+//   3(2) Bogacki-Shampine:  a = (1/2, 3/4), b = (2/9, 1/3, 4/9), a fourth
+//                           stage at the result, bh = (7/24, 1/4, 1/3, 1/8)
+mm_status embedded_step(mm_ctx *c, const float *base, float *out, double h, bool bs23, uint32_t flags, float *err)
+{
+    mmk::LocalParams p = local_params(c);
+    const bool comp = flags & MM_F_COMPENSATED;
+    const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
+    int *flag = c->at<int>(c->o_flag);
+    unsigned *emax = reinterpret_cast<unsigned *>(c->at<char>(c->o_flag) + 64);
+    const size_t S = 3 * (size_t)c->g.N;
+    float *stage[2] = {c->at<float>(c->o_rk), c->at<float>(c->o_rk) + S};
+    float *acc = c->at<float>(c->o_rk) + 2 * S, *eacc = c->at<float>(c->o_rk) + 3 * S;
+    struct St { float a, b, e; int last, err; };
+    static const St heun[2] = {{1.f, 0.5f, -0.5f, 0, 1}, {0.f, 0.5f, 0.5f, 1, 2}};
+    static const St bs[4] = {{0.5f, 2.f / 9.f, 2.f / 9.f - 7.f / 24.f, 0, 1},
+                             {0.75f, 1.f / 3.f, 1.f / 3.f - 0.25f, 0, 1},
+                             {0.f, 4.f / 9.f, 4.f / 9.f - 1.f / 3.f, 1, 1},
+                             {0.f, 0.f, -0.125f, 2, 2}};
+    const St *tab = bs23 ? bs : heun;
+    const int ns = bs23 ? 4 : 2;
+    MM_TRY(hipcheck(c, hipMemsetAsync(emax, 0, sizeof(unsigned), c->stream), "clear error maximum"));
+    const float *eval = base;
+    for (int i = 0; i < ns; ++i) {
+        float *Hd = nullptr;
+        MM_TRY(demag(c, eval, comp, &Hd));
+        p.stage_a = tab[i].a;
+        p.stage_b = tab[i].b;
+        p.stage_e = tab[i].e;
+        p.stage_first = i == 0;
+        p.stage_last = tab[i].last;
+        p.stage_err = tab[i].err;
+        float *o = tab[i].last == 1 ? out : (tab[i].last == 2 ? nullptr : stage[i & 1]);
+        MM_TRY(timed(c, MM_K_LOCAL, "embedded stage", [&] {
+            return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, eacc, (float)h,
+                                     renorm, o, flag, c->stream);
+        }));
+        if (o) eval = o;
+    }
+    MM_TRY(hipcheck(c, mmk::launch_errmax(eacc, c->g.N, emax, c->stream), "error maximum"));
+    unsigned bits = 0;
+    MM_TRY(hipcheck(c, hipMemcpyAsync(&bits, emax, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "read error"));
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "step sync"));
+    float e;
+    std::memcpy(&e, &bits, sizeof(e));
+    *err = e;
     return MM_OK;
 }
 
@@ -605,6 +657,59 @@ mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t f
             MM_TRY(hipcheck(c, hipGraphLaunch(exec, c->stream), "graph launch"));
     }
     return enqueue_steps(c, m, nsteps - done, dt, step_flags);
+}
+
+mm_status mm_step_adaptive(mm_ctx *c, float *m, double t_end, double *dt_io, double tol, uint32_t flags,
+                           int64_t max_steps, int64_t *accepted, int64_t *rejected)
+{
+    if (!c) return MM_EINVAL;
+    if (!dt_io || !(*dt_io > 0) || !std::isfinite(*dt_io)) return fail(c, MM_EINVAL, "*dt must be finite and > 0");
+    if (!(t_end >= 0) || !std::isfinite(t_end)) return fail(c, MM_EINVAL, "t_end must be finite and >= 0");
+    if (!(tol > 0) || !std::isfinite(tol)) return fail(c, MM_EINVAL, "tol must be finite and > 0");
+    if (max_steps < 1) return fail(c, MM_EINVAL, "max_steps must be >= 1");
+    const bool heun = flags & MM_F_HEUN, bs23 = flags & MM_F_BS23;
+    if (heun == bs23) return fail(c, MM_EINVAL, "exactly one of MM_F_HEUN and MM_F_BS23 selects the pair");
+    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_HEUN | MM_F_BS23))
+        return fail(c, MM_EINVAL, "unsupported flag bits 0x%x for adaptive steps", flags);
+    MM_TRY(check_step_args(c, m, 0, *dt_io, flags & ~uint32_t(MM_F_BS23)));
+    MM_TRY(set_device(c));
+    const int q = bs23 ? 2 : 1;  // order of the lower member
+    float *buf[2] = {m, c->at<float>(c->o_mtmp)};
+    int cur = 0;
+    double t = 0.0, dt = *dt_io;
+    int64_t acc = 0, rej = 0;
+    mm_status st = MM_OK;
+    while (t < t_end) {
+        if (acc + rej >= max_steps) {
+            st = fail(c, MM_ESTATE, "max_steps (%lld) attempts did not reach t_end", (long long)max_steps);
+            break;
+        }
+        const double h = (t + dt > t_end) ? t_end - t : dt;
+        float err = 0.f;
+        st = embedded_step(c, buf[cur], buf[cur ^ 1], h, bs23, flags, &err);
+        if (st != MM_OK) break;
+        if (!(err == err)) {
+            st = fail(c, MM_ENONFINITE, "non-finite error estimate at t = %g s", t);
+            break;
+        }
+        if ((double)err <= tol) {
+            cur ^= 1;
+            t += h;
+            ++acc;
+        } else {
+            ++rej;
+        }
+        double f = err > 0.f ? 0.9 * std::pow(tol / (double)err, 1.0 / (q + 1)) : 5.0;
+        f = std::min(5.0, std::max(0.2, f));
+        dt = h * f;
+    }
+    if (cur == 1)
+        MM_TRY(hipcheck(c, hipMemcpyAsync(m, buf[1], sizeof(float) * 3 * c->g.N, hipMemcpyDeviceToDevice, c->stream),
+                        "copy back state"));
+    *dt_io = dt;
+    if (accepted) *accepted = acc;
+    if (rejected) *rejected = rej;
+    return st;
 }
 
 mm_status mm_set_compensated(mm_ctx *c, int on)

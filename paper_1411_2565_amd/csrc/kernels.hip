@@ -644,19 +644,30 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     if (MODE == 2) {
         // one explicit Runge-Kutta stage (coefficients in p; the stage
         // states, like the step result, are renormalised unless renorm = 0)
-        float base[3][V], acc[3][V];
+        const bool write_state = p.stage_last != 2;
+        float base[3][V], acc[3][V], er[3][V];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            vload<V>(D.m_base + c * N + i0, base[c]);
-            if (p.stage_first) {
+            if (write_state) {
+                vload<V>(D.m_base + c * N + i0, base[c]);
+                if (p.stage_first) {
 #pragma unroll
-                for (int j = 0; j < V; ++j) acc[c][j] = base[c][j];
-            } else {
-                vload<V>(D.acc + c * N + i0, acc[c]);
+                    for (int j = 0; j < V; ++j) acc[c][j] = base[c][j];
+                } else {
+                    vload<V>(D.acc + c * N + i0, acc[c]);
+                }
+            }
+            if (p.stage_err) {
+                if (p.stage_first) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j) er[c][j] = 0.f;
+                } else {
+                    vload<V>(D.eacc + c * N + i0, er[c]);
+                }
             }
         }
-        const float wb = p.stage_b * dt, wa = p.stage_a * dt;
-        float o[3][V];
+        const float wb = p.stage_b * dt, wa = p.stage_a * dt, we = p.stage_e * dt;
+        float o[3][V], en[V] = {};
         bool bad = false;
 #pragma unroll
         for (int j = 0; j < V; ++j) {
@@ -665,6 +676,13 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
             const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
             const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
             const float kx = p.c1 * ax + p.c2 * bx, ky = p.c1 * ay + p.c2 * by, kz = p.c1 * az + p.c2 * bz;
+            if (p.stage_err) {
+                er[0][j] = fmaf(we, kx, er[0][j]);
+                er[1][j] = fmaf(we, ky, er[1][j]);
+                er[2][j] = fmaf(we, kz, er[2][j]);
+                en[j] = sqrtf(er[0][j] * er[0][j] + er[1][j] * er[1][j] + er[2][j] * er[2][j]);
+            }
+            if (!write_state) continue;
             acc[0][j] = fmaf(wb, kx, acc[0][j]);
             acc[1][j] = fmaf(wb, ky, acc[1][j]);
             acc[2][j] = fmaf(wb, kz, acc[2][j]);
@@ -689,6 +707,13 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
             o[1][j] = ny_;
             o[2][j] = nz_;
         }
+        if (p.stage_err == 1) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vstore<V>(D.eacc + c * N + i0, er[c]);
+        } else if (p.stage_err == 2) {
+            vstore<V>(D.eacc + i0, en);
+        }
+        if (!write_state) return;
         if (bad) *flag = 1;
         if (!p.stage_last) {
 #pragma unroll
@@ -1383,11 +1408,40 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
 }
 
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
-                        const float *h_map, const float *m_base, float *acc, float dt, int renorm, float *out_m,
-                        int *flag, hipStream_t s)
+                        const float *h_map, const float *m_base, float *acc, float *eacc, float dt, int renorm,
+                        float *out_m, int *flag, hipStream_t s)
 {
-    LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc};
+    LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc, eacc};
     return launch_local_batch(&d, 1, p, 15u, 2, dt, renorm, flag, s);
+}
+
+// Maximum of n non-negative floats (NaN propagates): grid-stride loop, LDS
+// tree per block, one atomicMax on the bit pattern per block.
+__global__ __launch_bounds__(kThreads) void k_errmax(const float *__restrict__ e, long long n,
+                                                     unsigned *__restrict__ out)
+{
+    __shared__ unsigned red[kThreads];
+    unsigned mx = 0u;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+        const unsigned v = __float_as_uint(e[i]);
+        mx = v > mx ? v : mx;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+hipError_t launch_errmax(const float *e, long long n, unsigned *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_errmax, dim3((unsigned)blocks), dim3(kThreads), 0, s, e, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,

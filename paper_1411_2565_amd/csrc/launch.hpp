@@ -25,8 +25,11 @@ struct LocalParams {
     // mode 2, one Runge-Kutta stage with k = f(m, H(m)) at this stage's state:
     //   acc' = (first ? m_base : acc) + stage_b dt k
     //   last: m_out = P(acc');  else: acc = acc', m_out = P(m_base + stage_a dt k)
-    float stage_a, stage_b;
-    int stage_first, stage_last;
+    //   stage_last = 2: error-only stage (no acc / m_out writes)
+    // with the embedded error estimate (stage_err = 1 or 2):
+    //   e' = (first ? 0 : eacc) + stage_e dt k;  1: eacc = e';  2: eacc[0][i] = |e'_i|
+    float stage_a, stage_b, stage_e;
+    int stage_first, stage_last, stage_err;
 };
 
 // Per-sample arguments of one pass.  A launch processes up to kMaxBatch
@@ -63,6 +66,7 @@ struct LocalDesc {
     float h0, h1, h2;  // uniform external field of this sample
     const float *m_base;  // mode 2: state at the start of the step
     float *acc;           // mode 2: m_base + dt sum_j b_j k_j so far (3N floats)
+    float *eacc;          // mode 2: dt sum_j e_j k_j so far (3N floats); per-cell norm at the error stage
 };
 template <typename D, int NB>
 struct Batch {
@@ -113,8 +117,11 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
 // one Runge-Kutta stage (all field terms; coefficients in p.stage_*): reads
 // m (the stage state), Hd = H_demag(m), m_base and acc; writes out_m and acc
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
-                        const float *h_map, const float *m_base, float *acc, float dt, int renorm, float *out_m,
-                        int *flag, hipStream_t s);
+                        const float *h_map, const float *m_base, float *acc, float *eacc, float dt, int renorm,
+                        float *out_m, int *flag, hipStream_t s);
+// out (one unsigned, zeroed by the caller) <- bits of max(e[0..n)) for e >= 0
+// or NaN (NaN wins: its bit pattern orders above every finite value)
+hipError_t launch_errmax(const float *e, long long n, unsigned *out, hipStream_t s);
 
 // adjoint of one Euler step: local part (a) and the non-local completion (b)
 hipError_t launch_adj_a(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,

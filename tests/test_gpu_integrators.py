@@ -1,8 +1,9 @@
 """GPU Runge-Kutta steps (MM_F_HEUN, MM_F_RK4) against the oracle's.
 
-Higher-order integrators are the paper's stated future work (Sec. 6); the
-tableaus are the textbook ones (Heun's explicit trapezoid, classic RK4), with
-stage states renormalised like the step result.  Tolerance as for the Euler
+Adaptive time steps are named as future work in Sec. 6; the fixed-step
+Heun and classic RK4 steps and the embedded 2(1) and 3(2) pairs used by the
+adaptive call take the textbook tableaus, with stage states renormalised
+like the step result.  Tolerance as for the Euler
 trajectories: 1e-4 relative L2 after the given number of steps.  Graph replay
 equals eager launches bit for bit.  At the thin film's configured dt, where
 explicit Euler is unstable for the highest exchange modes, RK4 keeps the
@@ -133,3 +134,53 @@ def test_rk4_energy_non_increasing_at_film_dt(gpu_lib):
     E = out["rk4"]
     assert np.all(np.diff(E) <= 1e-6 * np.abs(E[:-1]))
     assert E[-1] < E[0]
+
+
+@pytest.mark.parametrize("pair", ["heun_euler", "bs23"])
+def test_adaptive_matches_oracle(gpu_lib, pair):
+    """Adaptive steps (Sec. 6's future-work item) on the 16x16x2 block with
+    anisotropy and a field, to t = 1e-11 s at tol = 1e-5: the GPU's FP32
+    error estimate and the oracle's FP64 one drive the same controller, so
+    the step counts agree to a few percent and the end states to 1e-4."""
+    w = workloads.BLOCK_16x16x2
+    m0, _ = workloads.inputs(w)
+    h = (2e4, -1e4, 5e3)
+    kw = dict(Ms=w.Ms, A=w.A, Ku=3e4, u=(0.0, 0.6, 0.8), alpha=w.alpha)
+    fl = gpu_lib.MM_F_HEUN if pair == "heun_euler" else gpu_lib.MM_F_BS23
+    sim = gpu_lib.Sim(w.n, w.d, hext=h, **kw)
+    m = gpu(m0)
+    mf = host(m)
+    t_end, tol = 1e-11, 1e-5
+    dt, acc, rej = sim.run_adaptive(m, t_end, 1e-13, tol, fl)
+    sim.sync()
+    mo, dto, acco, rejo = oracle.Problem(w.n, w.d, hext=np.asarray(h), **kw).run_adaptive(mf, t_end, 1e-13, tol, pair)
+    e = rel(host(m), mo)
+    print(f"adaptive {pair} 16x16x2 to 1e-11 s: GPU {acc} accepted / {rej} rejected, oracle {acco} / {rejo}; "
+          f"rel L2 {e:.2e}")
+    assert abs(acc - acco) <= max(2, 0.05 * acco)
+    assert e < 1e-4
+    sim.close()
+
+
+def test_adaptive_argument_errors(gpu_lib):
+    b = gpu_lib
+    w = workloads.BLOCK_16x16x2
+    sim = b.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    m = gpu(workloads.inputs(w)[0])
+    dt, acc, rej = sim.run_adaptive(m, 0.0, 1e-13, 1e-5, b.MM_F_HEUN)
+    assert (acc, rej) == (0, 0)
+    for flags in (0, b.MM_F_HEUN | b.MM_F_BS23, b.MM_F_RK4, b.MM_F_HEUN | b.MM_F_GRAPH):
+        with pytest.raises(b.MMError) as ei:
+            sim.run_adaptive(m, 1e-12, 1e-13, 1e-5, flags)
+        assert ei.value.code == b.MM_EINVAL
+    with pytest.raises(b.MMError) as ei:
+        sim.run_adaptive(m, 1e-12, 1e-13, -1.0, b.MM_F_HEUN)
+    assert ei.value.code == b.MM_EINVAL
+    with pytest.raises(b.MMError) as ei:
+        sim.run_adaptive(m, 1e-9, 1e-13, 1e-5, b.MM_F_BS23, max_steps=3)
+    assert ei.value.code == b.MM_ESTATE
+    sim.sync()
+    import torch
+    assert torch.isfinite(m).all()
+    assert (torch.linalg.vector_norm(m, dim=0) - 1).abs().max() < 1e-5
+    sim.close()
