@@ -127,6 +127,8 @@ class Problem:
         N = nx * ny * nz
         Ms = np.asarray(self.Ms, dtype=np.float64)
         self._Ms = _f64(np.broadcast_to(Ms, (nz, ny, nx)) if Ms.ndim == 0 else Ms, (N,))
+        if not (np.all(np.isfinite(self._Ms)) and np.all(self._Ms >= 0)):
+            raise ValueError("Ms must be finite and >= 0 (0 marks a vacuum cell)")
         h = np.asarray(self.hext, dtype=np.float64)
         if h.shape == (3,):
             h = np.broadcast_to(h[:, None], (3, N))
@@ -239,7 +241,9 @@ class Problem:
 
     def adjoint(self, m0, nsteps, dt, target):
         """Loss 1/2 sum |m_T - t|^2 and its exact gradients w.r.t. m0, the
-        external-field map and the Ms map."""
+        external-field map and the Ms map (every cell magnetic)."""
+        if np.any(self._Ms == 0):
+            raise ValueError("the adjoint covers samples without vacuum cells")
         m0 = _f64(m0, self._shape())
         t = _f64(target, self._shape())
         gm = np.zeros(self._shape())

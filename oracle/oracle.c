@@ -250,6 +250,9 @@ void orc_tensor_table(int nx, int ny, int nz, double dx, double dy, double dz, d
 /*   H_i = - sum_j N(r_i - r_j) M_j,  M_j = Ms_j m_j,  self term included.   */
 /* N(o) is even in every axis for xx, yy, zz and odd in the two named axes   */
 /* for xy, xz, yz, which fixes the sign when a table entry is read at |o|.   */
+/* A cell is magnetic when its Ms > 0; Ms = 0 marks vacuum (see orc_heff). */
+static inline int magnetic(const orc_problem *p, size_t i) { return p->Ms[i] > 0.0; }
+
 /* ------------------------------------------------------------------------ */
 
 /* Apply the convolution to an arbitrary vector field v ([3][N]):
@@ -379,6 +382,10 @@ void orc_step_cells(const orc_problem *p, const double *m, const int64_t *obs, i
         const int64_t i = obs[q];
         const int ix = (int)(i % nx), iy = (int)((i / nx) % ny), iz = (int)(i / ((int64_t)nx * ny));
         const double mi[3] = {m[i], m[N + i], m[2 * N + i]};
+        if (!magnetic(p, (size_t)i)) {  /* vacuum: unchanged */
+            for (int c = 0; c < 3; ++c) out[c * nobs + q] = mi[c];
+            continue;
+        }
         double h[3] = {Hd[q], Hd[nobs + q], Hd[2 * nobs + q]};
         if (p->terms & ORC_T_EXCH) {
             const int coord[3] = {ix, iy, iz}, n[3] = {nx, ny, nz};
@@ -389,6 +396,7 @@ void orc_step_cells(const orc_problem *p, const double *m, const int64_t *obs, i
                     const int cc = coord[a] + s;
                     if (cc < 0 || cc >= n[a]) continue;
                     const int64_t j = i + s * stride[a];
+                    if (!magnetic(p, (size_t)j)) continue;
                     for (int c = 0; c < 3; ++c) h[c] += k * cd[a] * (m[c * N + j] - mi[c]);
                 }
         }
@@ -450,6 +458,40 @@ void orc_laplacian(int nx, int ny, int nz, double dx, double dy, double dz,
                 }
 }
 
+/* Non-regular geometry (named as future work in Sec. 6): a cell with      */
+/* Ms = 0 is vacuum.  It is no demag source (M = Ms m = 0); exchange omits   */
+/* vacuum neighbours, a free surface like the sample boundary; exchange and  */
+/* anisotropy fields are zero in vacuum (demag and Zeeman fields exist       */
+/* there); its m is never updated; energies skip it.                         */
+
+/* Six-neighbour Laplacian over magnetic cells: missing and vacuum          */
+/* neighbours are omitted; zero at vacuum cells.  Equals orc_laplacian when   */
+/* every cell is magnetic.                                                   */
+static void laplacian_magnetic(const orc_problem *p, const double *v, double *out)
+{
+    const int nx = p->nx, ny = p->ny, nz = p->nz;
+    const size_t N = (size_t)nx * ny * nz, sy = (size_t)nx, sz = (size_t)nx * ny;
+    const double cx = 1.0 / (p->dx * p->dx), cy = 1.0 / (p->dy * p->dy), cz = 1.0 / (p->dz * p->dz);
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int c = 0; c < 3; ++c)
+        for (int iz = 0; iz < nz; ++iz)
+            for (int iy = 0; iy < ny; ++iy)
+                for (int ix = 0; ix < nx; ++ix) {
+                    const size_t j = ((size_t)iz * ny + iy) * nx + ix, i = c * N + j;
+                    double s = 0.0;
+                    if (magnetic(p, j)) {
+                        const double vi = v[i];
+                        if (ix > 0 && magnetic(p, j - 1)) s += cx * (v[i - 1] - vi);
+                        if (ix < nx - 1 && magnetic(p, j + 1)) s += cx * (v[i + 1] - vi);
+                        if (iy > 0 && magnetic(p, j - sy)) s += cy * (v[i - sy] - vi);
+                        if (iy < ny - 1 && magnetic(p, j + sy)) s += cy * (v[i + sy] - vi);
+                        if (iz > 0 && magnetic(p, j - sz)) s += cz * (v[i - sz] - vi);
+                        if (iz < nz - 1 && magnetic(p, j + sz)) s += cz * (v[i + sz] - vi);
+                    }
+                    out[i] = s;
+                }
+}
+
 /* Effective field of eq. (2) restricted to the terms in the mask. */
 void orc_heff(const orc_problem *p, const double *m, int terms, double *H)
 {
@@ -458,14 +500,15 @@ void orc_heff(const orc_problem *p, const double *m, int terms, double *H)
     if (terms & ORC_T_DEMAG) orc_demag(p, m, H);
     if (terms & ORC_T_EXCH) {
         double *L = (double *)malloc(sizeof(double) * 3 * N);
-        orc_laplacian(p->nx, p->ny, p->nz, p->dx, p->dy, p->dz, m, L);
+        laplacian_magnetic(p, m, L);
         for (int c = 0; c < 3; ++c)
             for (size_t i = 0; i < N; ++i)
-                H[c * N + i] += 2.0 * p->A / (ORC_MU0 * p->Ms[i]) * L[c * N + i];
+                if (magnetic(p, i)) H[c * N + i] += 2.0 * p->A / (ORC_MU0 * p->Ms[i]) * L[c * N + i];
         free(L);
     }
     if (terms & ORC_T_ANIS) {
         for (size_t i = 0; i < N; ++i) {
+            if (!magnetic(p, i)) continue;
             const double mu = m[i] * p->u[0] + m[N + i] * p->u[1] + m[2 * N + i] * p->u[2];
             const double k = 2.0 * p->Ku / (ORC_MU0 * p->Ms[i]) * mu;
             for (int c = 0; c < 3; ++c) H[c * N + i] += k * p->u[c];
@@ -496,6 +539,10 @@ void orc_llg_rhs(const orc_problem *p, const double *m, const double *H, double 
     const double c1 = -p->gamma0 / (1.0 + p->alpha * p->alpha);
     const double c2 = p->alpha * c1;
     for (size_t i = 0; i < N; ++i) {
+        if (!magnetic(p, i)) {  /* vacuum: m does not move */
+            for (int c = 0; c < 3; ++c) f[c * N + i] = 0.0;
+            continue;
+        }
         const double mi[3] = {m[i], m[N + i], m[2 * N + i]};
         const double hi[3] = {H[i], H[N + i], H[2 * N + i]};
         double mxh[3], mxmxh[3];
@@ -516,6 +563,7 @@ void orc_step(const orc_problem *p, double *m, double dt, double *Hout)
     for (size_t i = 0; i < 3 * N; ++i) m[i] += dt * f[i];
     if (p->renorm)
         for (size_t i = 0; i < N; ++i) {
+            if (!magnetic(p, i)) continue;
             const double n = sqrt(m[i] * m[i] + m[N + i] * m[N + i] + m[2 * N + i] * m[2 * N + i]);
             m[i] /= n; m[N + i] /= n; m[2 * N + i] /= n;
         }
@@ -554,6 +602,7 @@ static void renormalise(const orc_problem *p, double *m, size_t N)
 {
     if (!p->renorm) return;
     for (size_t i = 0; i < N; ++i) {
+        if (!magnetic(p, i)) continue;
         const double n = sqrt(m[i] * m[i] + m[N + i] * m[N + i] + m[2 * N + i] * m[2 * N + i]);
         m[i] /= n; m[N + i] /= n; m[2 * N + i] /= n;
     }
@@ -733,11 +782,13 @@ void orc_energy(const orc_problem *p, const double *m, double out[5])
             for (int iz = 0; iz < nz; ++iz)
                 for (int iy = 0; iy < ny; ++iy)
                     for (int ix = 0; ix < nx; ++ix) {
-                        const size_t i = c * N + ((size_t)iz * ny + iy) * nx + ix;
+                        const size_t j = ((size_t)iz * ny + iy) * nx + ix, i = c * N + j;
+                        const size_t sz = (size_t)nx * ny;
                         double d;
-                        if (ix < nx - 1) { d = m[i + 1] - m[i]; eex += cx * d * d; }
-                        if (iy < ny - 1) { d = m[i + nx] - m[i]; eex += cy * d * d; }
-                        if (iz < nz - 1) { d = m[i + (size_t)nx * ny] - m[i]; eex += cz * d * d; }
+                        if (!magnetic(p, j)) continue;  /* pairs of two magnetic cells only */
+                        if (ix < nx - 1 && magnetic(p, j + 1)) { d = m[i + 1] - m[i]; eex += cx * d * d; }
+                        if (iy < ny - 1 && magnetic(p, j + nx)) { d = m[i + nx] - m[i]; eex += cy * d * d; }
+                        if (iz < nz - 1 && magnetic(p, j + sz)) { d = m[i + sz] - m[i]; eex += cz * d * d; }
                     }
         eex *= p->A * V;
     }
@@ -751,6 +802,7 @@ void orc_energy(const orc_problem *p, const double *m, double out[5])
     }
     if (p->terms & ORC_T_ANIS) {
         for (size_t i = 0; i < N; ++i) {
+            if (!magnetic(p, i)) continue;
             const double mu = m[i] * p->u[0] + m[N + i] * p->u[1] + m[2 * N + i] * p->u[2];
             ean += 1.0 - mu * mu;
         }

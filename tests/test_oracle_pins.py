@@ -504,3 +504,84 @@ def test_adjoint_matches_central_differences(renorm):
         e = 1e-5
         fd = (L(Ms_=Ms + e * v) - L(Ms_=Ms - e * v)) / (2 * e)
         np.testing.assert_allclose(np.sum(gms * v), fd, rtol=1e-7, atol=1e-14)
+
+
+# ------------------------------------------------- non-regular geometry --
+
+def _padded_pair():
+    """A 5x4x2 sample with Ms, field and state maps, and the same sample
+    embedded at offset (2, 1, 1) in a 9x7x4 grid whose other cells are
+    vacuum (Ms = 0) holding arbitrary m and field values."""
+    rng = np.random.default_rng(4)
+    n0, n1, off, d = (5, 4, 2), (9, 7, 4), (2, 1, 1), (4e-9, 5e-9, 3e-9)
+    sl = (Ellipsis, slice(off[2], off[2] + n0[2]), slice(off[1], off[1] + n0[1]), slice(off[0], off[0] + n0[0]))
+    m0 = rng.standard_normal((3, n0[2], n0[1], n0[0]))
+    m0 /= np.linalg.norm(m0, axis=0)
+    ms0 = 8e5 * (0.8 + 0.4 * rng.random((n0[2], n0[1], n0[0])))
+    h0 = 2e4 * rng.standard_normal((3, n0[2], n0[1], n0[0]))
+    m1 = rng.standard_normal((3, n1[2], n1[1], n1[0]))
+    m1 /= np.linalg.norm(m1, axis=0)
+    m1[sl] = m0
+    ms1 = np.zeros((n1[2], n1[1], n1[0]))
+    ms1[sl] = ms0
+    h1 = np.full((3, n1[2], n1[1], n1[0]), 3e4)
+    h1[sl] = h0
+    kw = dict(A=1.3e-11, Ku=3e4, u=(0.6, 0.0, 0.8), alpha=0.3)
+    P0 = oracle.Problem(n0, d, Ms=ms0, hext=h0, **kw)
+    P1 = oracle.Problem(n1, d, Ms=ms1, hext=h1, **kw)
+    return P0, P1, m0, m1, sl, ms1 > 0
+
+
+def test_vacuum_padding_is_invisible():
+    """Vacuum cells are no demag source, cut exchange like a free surface and
+    do not move: padding a sample with vacuum leaves its fields, trajectory
+    (Euler and adaptive) and energies unchanged, and the vacuum cells'
+    state untouched."""
+    P0, P1, m0, m1, sl, mag = _padded_pair()
+    np.testing.assert_allclose(P1.heff(m1)[sl], P0.heff(m0), rtol=0, atol=1e-9)
+    r0, r1 = P0.run(m0, 20, 2e-14), P1.run(m1, 20, 2e-14)
+    np.testing.assert_allclose(r1[sl], r0, rtol=0, atol=1e-13)
+    assert np.array_equal(r1[:, ~mag], m1[:, ~mag])
+    np.testing.assert_allclose(P1.energy(m1), P0.energy(m0), rtol=1e-12)
+    a0 = P0.run_adaptive(m0, 5e-13, 1e-14, 1e-5, "bs23")
+    a1 = P1.run_adaptive(m1, 5e-13, 1e-14, 1e-5, "bs23")
+    assert a0[2:] == a1[2:]
+    np.testing.assert_allclose(a1[0][sl], a0[0], rtol=0, atol=1e-13)
+
+
+def test_vacuum_cells_have_only_stray_and_applied_fields():
+    """In vacuum the exchange and anisotropy fields vanish; the demag (stray)
+    field and the applied field remain."""
+    P0, P1, m0, m1, sl, mag = _padded_pair()
+    H = P1.heff(m1, oracle.T_EXCH | oracle.T_ANIS)
+    assert np.all(H[:, ~mag] == 0)
+    Hd = P1.heff(m1, oracle.T_DEMAG)
+    assert np.abs(Hd[:, ~mag]).max() > 1e3
+    Hz = P1.heff(m1, oracle.T_ZEEMAN)
+    np.testing.assert_array_equal(Hz, np.asarray(P1.hext))
+
+
+def test_cubic_body_average_demag_is_one_third():
+    """A body with the symmetry of the cube (here a staircase sphere of
+    radius 8 cells cut from a 18^3 grid by the Ms map) has equal average
+    demag factors, and they sum to one: uniform M gives a volume-averaged
+    field of exactly -M/3 inside."""
+    R, N = 8, 18
+    c = np.arange(N) + 0.5 - N / 2
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    inside = x * x + y * y + z * z < R * R
+    m = np.zeros((3, N, N, N))
+    m[2] = 1.0
+    P = oracle.Problem((N, N, N), (5e-9,) * 3, Ms=np.where(inside, 8e5, 0.0), A=1.3e-11, terms=oracle.T_DEMAG)
+    Hd = P.demag(m)
+    assert inside.sum() == 2176
+    np.testing.assert_allclose(Hd[2][inside].mean() / 8e5, -1.0 / 3.0, rtol=1e-10)
+    assert abs(Hd[0][inside].mean()) < 1e-10 * 8e5
+
+
+def test_ms_map_must_be_non_negative():
+    with pytest.raises(ValueError):
+        oracle.Problem((2, 2, 1), (5e-9,) * 3, Ms=np.array([[[1e5, -1.0], [1e5, 1e5]]]))
+    P0, P1, m0, m1, sl, mag = _padded_pair()
+    with pytest.raises(ValueError):
+        P1.adjoint(m1, 2, 1e-14, m1)
