@@ -111,8 +111,18 @@ mm_status mm_set_workspace(mm_ctx *c, void *dev_ptr, size_t bytes);
  * gamma0 > 0. */
 mm_status mm_set_material(mm_ctx *c, const mm_material *mat);
 
-/* Per-cell saturation magnetisation map (N floats, device, all > 0), copied
- * into the workspace on the stream; NULL returns to the uniform Ms. */
+/* Per-cell saturation magnetisation map (N floats, device, A/m), copied into
+ * the workspace; NULL returns to the uniform Ms.  Cells with Ms = 0 are
+ * vacuum, which makes the geometry non-regular (named as future work in
+ * Sec. 6): they are no demag source, exchange omits them as neighbours (a
+ * free surface, as at the sample boundary), exchange and anisotropy fields
+ * are zero there (mm_compute_heff returns the demag and applied fields),
+ * their state is never changed, and mm_reduce skips them (energies, and the
+ * mean magnetisation is over magnetic cells).  The state in vacuum cells
+ * must still be finite.  Values must be finite and >= 0, checked here
+ * (MM_EINVAL otherwise, the uniform Ms stays); the check synchronises the
+ * stream.  With vacuum cells, mm_forward_store and mm_adjoint_step return
+ * MM_EUNSUP. */
 mm_status mm_set_ms_map(mm_ctx *c, const float *ms_dev);
 
 /* Uniform external field (Sec. 2, H_extern), A/m. */

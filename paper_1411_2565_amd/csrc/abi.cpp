@@ -54,6 +54,7 @@ struct mm_ctx {
     size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_rk = 0, o_T = 0, o_tA = 0, o_tB = 0;
     size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
+    bool vacuum = false;       // the Ms map holds vacuum cells (Ms = 0)
     std::string err;
     // captured step chunks (MM_F_GRAPH): kernel arguments (state pointer,
     // material, fields, maps, dt) are baked in, so every setter drops them
@@ -403,10 +404,19 @@ mm_status mm_set_ms_map(mm_ctx *c, const float *ms)
     }
     if (!aligned16(ms)) return fail(c, MM_EINVAL, "Ms map must be 16-byte aligned");
     MM_TRY(set_device(c));
+    c->drop_graphs();
+    c->ms_map = false;
     MM_TRY(hipcheck(c, hipMemcpyAsync(c->at<float>(c->o_ms), ms, sizeof(float) * c->g.N, hipMemcpyDeviceToDevice,
                                       c->stream), "copy Ms map"));
+    unsigned *chk = reinterpret_cast<unsigned *>(c->at<char>(c->o_flag) + 128);
+    unsigned res[2] = {0u, 0u};
+    MM_TRY(hipcheck(c, hipMemsetAsync(chk, 0, sizeof(res), c->stream), "clear map check"));
+    MM_TRY(hipcheck(c, mmk::launch_map_check(c->at<float>(c->o_ms), c->g.N, chk, c->stream), "check Ms map"));
+    MM_TRY(hipcheck(c, hipMemcpyAsync(res, chk, sizeof(res), hipMemcpyDeviceToHost, c->stream), "read map check"));
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "map check sync"));
+    if (res[0]) return fail(c, MM_EINVAL, "Ms map values must be finite and >= 0 (0 marks vacuum)");
     c->ms_map = true;
-    c->drop_graphs();
+    c->vacuum = res[1] != 0;
     return MM_OK;
 }
 
@@ -727,6 +737,7 @@ mm_status mm_forward_store(mm_ctx *c, float *m, int64_t nsteps, double dt, uint3
     MM_TRY(check_step_args(c, m, nsteps, dt, flags));
     if (flags & (MM_F_HEUN | MM_F_RK4))
         return fail(c, MM_EUNSUP, "the stored replay and the adjoint cover the Euler step only");
+    if (c->ms_map && c->vacuum) return fail(c, MM_EUNSUP, "the adjoint covers samples without vacuum cells");
     if (nsteps > 0 && (!m_traj || !hd_traj || !aligned16(m_traj) || !aligned16(hd_traj)))
         return fail(c, MM_EINVAL, "trajectory buffers must be 16-byte aligned device pointers");
     MM_TRY(set_device(c));
@@ -747,6 +758,7 @@ mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float 
     if (!c) return MM_EINVAL;
     MM_TRY(check_step_args(c, m_n, 1, dt, flags));
     if (flags & (MM_F_HEUN | MM_F_RK4)) return fail(c, MM_EUNSUP, "the adjoint covers the Euler step only");
+    if (c->ms_map && c->vacuum) return fail(c, MM_EUNSUP, "the adjoint covers samples without vacuum cells");
     if (!hd_n || !lam || !aligned16(hd_n) || !aligned16(lam))
         return fail(c, MM_EINVAL, "hd_n and lam must be 16-byte aligned device pointers");
     if ((g_hext && !aligned16(g_hext)) || (g_ms && !aligned16(g_ms)))

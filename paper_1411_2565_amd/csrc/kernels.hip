@@ -558,15 +558,25 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
             for (int j = 0; j < V; ++j) h[c][j] = 0.f;
         }
     }
+    // With an Ms map, cells with Ms = 0 are vacuum (non-regular geometry):
+    // no exchange or anisotropy field there, exchange skips vacuum
+    // neighbours (a free surface), and their state never moves.
     float inv_ms[V];
+    bool mag[V];
     if (ms_map) {
         float s[V];
         vload<V>(ms_map + i0, s);
 #pragma unroll
-        for (int j = 0; j < V; ++j) inv_ms[j] = 1.0f / s[j];
+        for (int j = 0; j < V; ++j) {
+            mag[j] = s[j] > 0.f;
+            inv_ms[j] = mag[j] ? 1.0f / s[j] : 0.f;
+        }
     } else {
 #pragma unroll
-        for (int j = 0; j < V; ++j) inv_ms[j] = 1.0f / p.ms;
+        for (int j = 0; j < V; ++j) {
+            mag[j] = true;
+            inv_ms[j] = 1.0f / p.ms;
+        }
     }
     if (terms & 1u) {
         float lap[3][V];
@@ -575,29 +585,48 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
 #pragma unroll
             for (int j = 0; j < V; ++j) lap[c][j] = 0.f;
         // x neighbours: inside the vector, plus one scalar on each side
+        const bool has_l = x0 > 0 && (!ms_map || ms_map[i0 - 1] > 0.f);
+        const bool has_r = x0 + V < g.nx && (!ms_map || ms_map[i0 + V] > 0.f);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float left = x0 > 0 ? m[c * N + i0 - 1] : 0.f;
-            const float right = x0 + V < g.nx ? m[c * N + i0 + V] : 0.f;
+            const float left = has_l ? m[c * N + i0 - 1] : 0.f;
+            const float right = has_r ? m[c * N + i0 + V] : 0.f;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const float a = mc[c][j];
                 float s = 0.f;
-                if (j > 0) s += mc[c][j - 1] - a;
-                else if (x0 > 0) s += left - a;
-                if (j < V - 1) s += mc[c][j + 1] - a;
-                else if (x0 + V < g.nx) s += right - a;
+                if (j > 0) {
+                    if (mag[j - 1]) s += mc[c][j - 1] - a;
+                } else if (has_l) {
+                    s += left - a;
+                }
+                if (j < V - 1) {
+                    if (mag[j + 1]) s += mc[c][j + 1] - a;
+                } else if (has_r) {
+                    s += right - a;
+                }
                 lap[c][j] = p.ax * s;
             }
         }
         const long long sy = g.nx, sz = (long long)g.nx * g.ny;
         auto add = [&](long long off, float w) {
+            bool nbm[V];
+            if (ms_map) {
+                float sn[V];
+                vload<V>(ms_map + i0 + off, sn);
+#pragma unroll
+                for (int j = 0; j < V; ++j) nbm[j] = sn[j] > 0.f;
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) nbm[j] = true;
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float nb[V];
                 vload<V>(m + c * N + i0 + off, nb);
 #pragma unroll
-                for (int j = 0; j < V; ++j) lap[c][j] = fmaf(w, nb[j] - mc[c][j], lap[c][j]);
+                for (int j = 0; j < V; ++j)
+                    if (nbm[j]) lap[c][j] = fmaf(w, nb[j] - mc[c][j], lap[c][j]);
             }
         };
         if (y > 0) add(-sy, p.ay);
@@ -607,11 +636,13 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int j = 0; j < V; ++j) h[c][j] = fmaf(lap[c][j], inv_ms[j], h[c][j]);
+            for (int j = 0; j < V; ++j)
+                if (mag[j]) h[c][j] = fmaf(lap[c][j], inv_ms[j], h[c][j]);
     }
     if (terms & 4u) {
 #pragma unroll
         for (int j = 0; j < V; ++j) {
+            if (!mag[j]) continue;
             const float k = p.ku2 * inv_ms[j] * (mc[0][j] * p.u0 + mc[1][j] * p.u1 + mc[2][j] * p.u2);
             h[0][j] = fmaf(k, p.u0, h[0][j]);
             h[1][j] = fmaf(k, p.u1, h[1][j]);
@@ -676,6 +707,13 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
             const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
             const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
             const float kx = p.c1 * ax + p.c2 * bx, ky = p.c1 * ay + p.c2 * by, kz = p.c1 * az + p.c2 * bz;
+            if (!mag[j]) {  // vacuum: k = 0, the state stays as it is
+                en[j] = p.stage_err ? sqrtf(er[0][j] * er[0][j] + er[1][j] * er[1][j] + er[2][j] * er[2][j]) : 0.f;
+                o[0][j] = mx;
+                o[1][j] = my;
+                o[2][j] = mz;
+                continue;
+            }
             if (p.stage_err) {
                 er[0][j] = fmaf(we, kx, er[0][j]);
                 er[1][j] = fmaf(we, ky, er[1][j]);
@@ -728,6 +766,12 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
 #pragma unroll
     for (int j = 0; j < V; ++j) {
         const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
+        if (!mag[j]) {  // vacuum: the state stays as it is
+            o[0][j] = mx;
+            o[1][j] = my;
+            o[2][j] = mz;
+            continue;
+        }
         const float hx = h[0][j], hy = h[1][j], hz = h[2][j];
         // m x H and m x (m x H)
         const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
@@ -908,7 +952,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_b(Geo g, LocalParams p, const 
 // a9: FP64 energy terms and mean magnetisation.  Per-block partial sums in a
 // fixed order, then one block sums the partials: deterministic.
 // ------------------------------------------------------------------------
-constexpr int kEq = 7;  // e_ex, e_d, e_an, e_z, sum mx, sum my, sum mz
+constexpr int kEq = 8;  // e_ex, e_d, e_an, e_z, sum mx, sum my, sum mz, magnetic cells
 
 __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, const float *__restrict__ m,
                                                      const float *__restrict__ Hd,
@@ -917,7 +961,7 @@ __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, cons
                                                      double *__restrict__ partials)
 {
     __shared__ double red[kEq][kThreads];
-    double acc[kEq] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[kEq] = {0, 0, 0, 0, 0, 0, 0, 0};
     const long long N = g.N;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < N;
          i += (long long)gridDim.x * kThreads) {
@@ -926,8 +970,10 @@ __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, cons
         const long long r = i / g.nx;
         const int y = (int)(r % g.ny), z = (int)(r / g.ny);
         const double ms = ms_map ? (double)ms_map[i] : p.ms;
+        if (!(ms > 0.0)) continue;  // vacuum: no energy, not in the mean
         if (p.terms & 1u) {
             auto pair = [&](long long j, double w) {
+                if (ms_map && !(ms_map[j] > 0.f)) return;  // pairs of magnetic cells only
                 const double dx = m[j] - mx, dy = m[N + j] - my, dz = m[2 * N + j] - mz;
                 acc[0] += w * (dx * dx + dy * dy + dz * dz);
             };
@@ -952,6 +998,7 @@ __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, cons
         acc[4] += mx;
         acc[5] += my;
         acc[6] += mz;
+        acc[7] += 1.0;
     }
 #pragma unroll
     for (int q = 0; q < kEq; ++q) red[q][threadIdx.x] = acc[q];
@@ -971,7 +1018,7 @@ __global__ __launch_bounds__(kThreads) void k_energy_final(int nblk, EnergyParam
                                                            double *__restrict__ out)
 {
     __shared__ double red[kEq][kThreads];
-    double acc[kEq] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[kEq] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += kThreads)
 #pragma unroll
         for (int q = 0; q < kEq; ++q) acc[q] += partials[(long long)b * kEq + q];
@@ -995,9 +1042,10 @@ __global__ __launch_bounds__(kThreads) void k_energy_final(int nblk, EnergyParam
         out[2] = ean;
         out[3] = ez;
         out[4] = eex + ed + ean + ez;
-        out[5] = red[4][0] / (double)N;
-        out[6] = red[5][0] / (double)N;
-        out[7] = red[6][0] / (double)N;
+        const double cells = red[7][0];  // magnetic cells (all N without vacuum)
+        out[5] = cells > 0.0 ? red[4][0] / cells : 0.0;
+        out[6] = cells > 0.0 ? red[5][0] / cells : 0.0;
+        out[7] = cells > 0.0 ? red[6][0] / cells : 0.0;
     }
 }
 
@@ -1433,6 +1481,44 @@ __global__ __launch_bounds__(kThreads) void k_errmax(const float *__restrict__ e
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicMax(out, red[0]);
+}
+
+// Checks an Ms map: out[0] |= 1 if some value is negative, NaN or infinite
+// (its bit pattern is above that of the largest finite float), out[1] |= 1
+// if some value is zero (a vacuum cell).
+__global__ __launch_bounds__(kThreads) void k_map_check(const float *__restrict__ v, long long n,
+                                                        unsigned *__restrict__ out)
+{
+    __shared__ unsigned red[2][kThreads];
+    unsigned bad = 0u, zero = 0u;
+    for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
+        const unsigned b = __float_as_uint(v[i]);
+        bad |= b > 0x7f7fffffu ? 1u : 0u;
+        zero |= b == 0u ? 1u : 0u;
+    }
+    red[0][threadIdx.x] = bad;
+    red[1][threadIdx.x] = zero;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            red[0][threadIdx.x] |= red[0][threadIdx.x + w];
+            red[1][threadIdx.x] |= red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (red[0][0]) atomicOr(out, 1u);
+        if (red[1][0]) atomicOr(out + 1, 1u);
+    }
+}
+
+hipError_t launch_map_check(const float *v, long long n, unsigned *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + kThreads - 1) / kThreads;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_map_check, dim3((unsigned)blocks), dim3(kThreads), 0, s, v, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_errmax(const float *e, long long n, unsigned *out, hipStream_t s)
