@@ -325,6 +325,30 @@ def integrator_rates(binding, steps=200):
     return out
 
 
+def geometry_rate(binding, steps=500):
+    """Step time on the 256x256x32 grid with the inscribed elliptic cylinder
+    as magnetic body (vacuum outside, Ms map), against the full block: the
+    cost of non-regular geometry on the same FFT grid."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    w = workloads.BLOCK_256x256x32
+    m0, _ = workloads.inputs(w)
+    ms = workloads.disk_ms_map(w.n, w.Ms)
+    out = {"workload": "256x256x32 grid, 5 nm cubes, disk of 1.28 um diameter through all 32 layers "
+                       "(vacuum outside), dt=1e-13", "magnetic_cells": int((ms > 0).sum()), "steps": steps}
+    for name, use_map in (("full_block", False), ("disk", True)):
+        sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, device=0)
+        if use_map:
+            sim.set_ms_map(torch.tensor(ms, dtype=torch.float32, device="cuda:0"))
+        m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+        sim.step(m, 20, w.dt)
+        t = timed_steps(sim, m, steps, w.dt, 0)
+        sim.sync()
+        sim.close()
+        out[name + "_us_per_step"] = round(1e6 * t / steps, 1)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,7 +363,9 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="also time the N^3 cube size sweep and the standard problem #4 film")
     ap.add_argument("--integrators", action="store_true",
-                    help="also time the Heun and RK4 steps on the block")
+                    help="also time the Heun, RK4 and adaptive steps on the block")
+    ap.add_argument("--geometry", action="store_true",
+                    help="also time a disk (vacuum outside) on the block's grid")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (3 times) for PMC counter calibration")
     args = ap.parse_args()
@@ -420,6 +446,11 @@ def main():
         print("bench: Runge-Kutta steps", file=sys.stderr, flush=True)
         rk = integrator_rates(binding)
 
+    geo = None
+    if args.geometry:
+        print("bench: non-regular geometry", file=sys.stderr, flush=True)
+        geo = geometry_rate(binding)
+
     cpu = None
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
@@ -454,6 +485,7 @@ def main():
         "size_sweep": sweep,
         "sp4": sp4,
         "integrators": rk,
+        "geometry": geo,
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:
