@@ -349,6 +349,31 @@ def geometry_rate(binding, steps=500):
     return out
 
 
+def tuning_rates(binding, steps=300):
+    """Autotuned launch shapes against the defaults: per-step time on the
+    256x256x32 block and on the 128^3 and 256^3 cubes of the sweep."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    rows = []
+    for w in (workloads.BLOCK_256x256x32, workloads.table1_cube(128), workloads.table1_cube(256)):
+        m0, _ = workloads.inputs(w)
+        sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=w.Ku, u=w.u, alpha=w.alpha, device=0)
+        m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+        n = steps if w.N <= 2097152 else max(20, steps // 8)
+        sim.step(m, 20, w.dt)
+        t_def = timed_steps(sim, m, n, w.dt, 0)
+        choice = sim.autotune(None)
+        sim.step(m, 20, w.dt)
+        t_tun = timed_steps(sim, m, n, w.dt, 0)
+        sim.sync()
+        sim.close()
+        del m
+        torch.cuda.empty_cache()
+        rows.append({"workload": w.name, "choice_xyz": list(choice), "steps": n,
+                     "default_us_per_step": round(1e6 * t_def / n, 1), "tuned_us_per_step": round(1e6 * t_tun / n, 1)})
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +391,8 @@ def main():
                     help="also time the Heun, RK4 and adaptive steps on the block")
     ap.add_argument("--geometry", action="store_true",
                     help="also time a disk (vacuum outside) on the block's grid")
+    ap.add_argument("--tune", action="store_true",
+                    help="also autotune the launch shapes and time them against the defaults")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (3 times) for PMC counter calibration")
     args = ap.parse_args()
@@ -446,6 +473,11 @@ def main():
         print("bench: Runge-Kutta steps", file=sys.stderr, flush=True)
         rk = integrator_rates(binding)
 
+    tun = None
+    if args.tune:
+        print("bench: autotuned launch shapes", file=sys.stderr, flush=True)
+        tun = tuning_rates(binding)
+
     geo = None
     if args.geometry:
         print("bench: non-regular geometry", file=sys.stderr, flush=True)
@@ -486,6 +518,7 @@ def main():
         "sp4": sp4,
         "integrators": rk,
         "geometry": geo,
+        "tuning": tun,
     }
     print(json.dumps(line), flush=True)
     if args.calib_copy:

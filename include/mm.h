@@ -186,6 +186,30 @@ mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
  * adjoint steps), in addition to per-call MM_F_COMPENSATED. */
 mm_status mm_set_compensated(mm_ctx *c, int on);
 
+/* Launch-shape tuning of the FFT passes (the paper leaves FFT performance to
+ * its FFT library, Sec. 3).  Each of the x passes, the y
+ * passes and the z pass has MM_TUNE_VARIANTS launch shapes: x = lines per
+ * block (16, 8, 32), y = lines per thread group (1, 2, 4), z = points per
+ * thread and columns per block (default; the other of 4/8 points; half the
+ * columns).  A variant applies to single-sample launches whose line has 64
+ * points or more.  The x and y variants give results identical bit for bit
+ * to the default; the z variants differ in rounding only (another radix
+ * split).  The choice is kept by the context (graphs are re-captured). */
+#define MM_TUNE_VARIANTS 3
+/* Set the choice {x, y, z}, each in [0, MM_TUNE_VARIANTS). */
+mm_status mm_set_tuning(mm_ctx *c, const int32_t choice[3]);
+mm_status mm_get_tuning(const mm_ctx *c, int32_t choice[3]);
+/* Choose the fastest variant of each pass for this geometry and GPU.  If
+ * cache_path names a text file holding a line "<gfx arch> nx ny nz x y z"
+ * for this device and geometry, that choice is taken without timing;
+ * otherwise every variant runs 2 + 10 times on zeroed workspace buffers,
+ * timed with HIP events on the context's stream (synchronous), and the
+ * winners are appended to the file when cache_path is not NULL (MM_EINVAL
+ * if it cannot be written).  Needs the workspace; overwrites the FFT
+ * intermediates and the second state buffer, not the tensor, maps or any
+ * caller buffer.  choice_out (may be NULL) receives {x, y, z}. */
+mm_status mm_autotune(mm_ctx *c, const char *cache_path, int32_t choice_out[3]);
+
 /* Adaptive time steps (named as future work in Sec. 6): advance m_dev in
  * place from t = 0 to t_end (s) with an embedded explicit Runge-Kutta pair
  * of the right-hand side of eq. (3), selected by exactly one of

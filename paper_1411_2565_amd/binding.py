@@ -69,6 +69,9 @@ def load():
         "mm_sync": [_P],
         "mm_kernel_timing": [_P, ctypes.c_int],
         "mm_set_compensated": [_P, ctypes.c_int],
+        "mm_set_tuning": [_P, ctypes.POINTER(ctypes.c_int32)],
+        "mm_get_tuning": [_P, ctypes.POINTER(ctypes.c_int32)],
+        "mm_autotune": [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)],
         "mm_step_adaptive": [_P, _P, ctypes.c_double, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                              ctypes.c_uint32, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                              ctypes.POINTER(ctypes.c_int64)],
@@ -211,6 +214,28 @@ def mm_sync(ctx):
 
 def mm_set_compensated(ctx, on):
     _check(ctx, load().mm_set_compensated(ctx, int(bool(on))), "mm_set_compensated")
+
+
+MM_TUNE_VARIANTS = 3
+
+
+def mm_set_tuning(ctx, choice):
+    arr = (ctypes.c_int32 * 3)(*[int(v) for v in choice])
+    _check(ctx, load().mm_set_tuning(ctx, arr), "mm_set_tuning")
+
+
+def mm_get_tuning(ctx):
+    arr = (ctypes.c_int32 * 3)()
+    _check(ctx, load().mm_get_tuning(ctx, arr), "mm_get_tuning")
+    return tuple(arr)
+
+
+def mm_autotune(ctx, cache_path=None):
+    """Fastest launch-shape variant per pass for this geometry (x, y, z)."""
+    arr = (ctypes.c_int32 * 3)()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _check(ctx, load().mm_autotune(ctx, path, arr), "mm_autotune")
+    return tuple(arr)
 
 
 def mm_step_adaptive(ctx, m, t_end, dt, tol, flags, max_steps, N):
@@ -431,6 +456,13 @@ class Sim:
         """Adaptive steps of m (in place) up to t_end: (dt, accepted, rejected)."""
         self._s()
         return mm_step_adaptive(self.ctx, m, t_end, dt0, tol, flags, max_steps, self.N)
+
+    def autotune(self, cache_path=None):
+        self._s()
+        return mm_autotune(self.ctx, cache_path)
+
+    def set_tuning(self, choice):
+        mm_set_tuning(self.ctx, choice)
 
     def reduce(self, m):
         import torch

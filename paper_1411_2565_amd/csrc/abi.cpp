@@ -55,6 +55,7 @@ struct mm_ctx {
     size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
     bool vacuum = false;       // the Ms map holds vacuum cells (Ms = 0)
+    int tune[3] = {0, 0, 0};   // launch-shape variants of the x, y and z passes
     std::string err;
     // captured step chunks (MM_F_GRAPH): kernel arguments (state pointer,
     // material, fields, maps, dt) are baked in, so every setter drops them
@@ -270,11 +271,12 @@ mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd, float *out = n
     const float *msm = unit_ms ? nullptr : ms_map_ptr(c);
     const float ms = unit_ms ? 1.0f : (float)c->mat.Ms;
     comp = comp || c->compensated;
-    MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, msm, ms, S1, s); }));
-    MM_TRY(timed(c, MM_K_YFWD, "yfwd", [&] { return mmk::launch_yfwd(g, S1, S2, s); }));
-    MM_TRY(timed(c, MM_K_ZCONV, "zconv", [&] { return mmk::launch_zconv(g, S2, K, comp, s); }));
-    MM_TRY(timed(c, MM_K_YINV, "yinv", [&] { return mmk::launch_yinv(g, S2, S1, s); }));
-    MM_TRY(timed(c, MM_K_XINV, "xinv", [&] { return mmk::launch_xinv(g, S1, H, s); }));
+    const int *tv = c->tune;
+    MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, msm, ms, S1, s, tv[0]); }));
+    MM_TRY(timed(c, MM_K_YFWD, "yfwd", [&] { return mmk::launch_yfwd(g, S1, S2, s, tv[1]); }));
+    MM_TRY(timed(c, MM_K_ZCONV, "zconv", [&] { return mmk::launch_zconv(g, S2, K, comp, s, tv[2]); }));
+    MM_TRY(timed(c, MM_K_YINV, "yinv", [&] { return mmk::launch_yinv(g, S2, S1, s, tv[1]); }));
+    MM_TRY(timed(c, MM_K_XINV, "xinv", [&] { return mmk::launch_xinv(g, S1, H, s, tv[0]); }));
     *Hd = H;
     return MM_OK;
 }
@@ -720,6 +722,127 @@ mm_status mm_step_adaptive(mm_ctx *c, float *m, double t_end, double *dt_io, dou
     if (accepted) *accepted = acc;
     if (rejected) *rejected = rej;
     return st;
+}
+
+mm_status mm_set_tuning(mm_ctx *c, const int32_t choice[3])
+{
+    if (!c || !choice) return MM_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (choice[k] < 0 || choice[k] >= MM_TUNE_VARIANTS)
+            return fail(c, MM_EINVAL, "tuning choice %d out of range [0, %d)", choice[k], MM_TUNE_VARIANTS);
+    for (int k = 0; k < 3; ++k) c->tune[k] = choice[k];
+    c->drop_graphs();
+    return MM_OK;
+}
+
+mm_status mm_get_tuning(const mm_ctx *c, int32_t choice[3])
+{
+    if (!c || !choice) return MM_EINVAL;
+    for (int k = 0; k < 3; ++k) choice[k] = c->tune[k];
+    return MM_OK;
+}
+
+mm_status mm_autotune(mm_ctx *c, const char *cache_path, int32_t choice_out[3])
+{
+    if (!c) return MM_EINVAL;
+    MM_TRY(need_ws(c));
+    MM_TRY(set_device(c));
+    hipDeviceProp_t prop;
+    MM_TRY(hipcheck(c, hipGetDeviceProperties(&prop, c->device), "device properties"));
+    std::string arch(prop.gcnArchName);
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    const mmk::Geo &g = c->g;
+    int best[3] = {0, 0, 0};
+    bool found = false;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char a[256];
+            int nx, ny, nz, v0, v1, v2;
+            while (std::fscanf(f, "%255s %d %d %d %d %d %d", a, &nx, &ny, &nz, &v0, &v1, &v2) == 7) {
+                if (arch == a && nx == g.nx && ny == g.ny && nz == g.nz && v0 >= 0 && v0 < MM_TUNE_VARIANTS &&
+                    v1 >= 0 && v1 < MM_TUNE_VARIANTS && v2 >= 0 && v2 < MM_TUNE_VARIANTS) {
+                    best[0] = v0; best[1] = v1; best[2] = v2;
+                    found = true;  // the last matching line wins
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    if (!found) {
+        // time each variant of each pass on zeroed buffers (the values do
+        // not matter for the time; zeros keep every intermediate finite)
+        float2 *S1 = c->at<float2>(c->o_S1), *S2 = c->at<float2>(c->o_S2);
+        float *mz = c->at<float>(c->o_mtmp), *H = c->at<float>(c->o_S2);
+        const float *K = c->at<float>(c->o_K);
+        hipStream_t st = c->stream;
+        const size_t s1b = sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.ny;
+        const size_t s2b = sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.Py;
+        MM_TRY(hipcheck(c, hipMemsetAsync(mz, 0, sizeof(float) * 3 * (size_t)g.N, st), "clear state"));
+        MM_TRY(hipcheck(c, hipMemsetAsync(S1, 0, s1b, st), "clear S1"));
+        MM_TRY(hipcheck(c, hipMemsetAsync(S2, 0, s2b, st), "clear S2"));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        MM_TRY(hipcheck(c, hipEventCreate(&e0), "event"));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return fail(c, MM_EHIP, "event");
+        }
+        mm_status status = MM_OK;
+        auto time_it = [&](auto &&launch, float *ms_out) -> hipError_t {
+            for (int r = 0; r < 2; ++r)
+                if (hipError_t e = launch(); e != hipSuccess) return e;
+            hipError_t e = hipEventRecord(e0, st);
+            for (int r = 0; r < 10 && e == hipSuccess; ++r) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            if (e == hipSuccess) e = hipEventElapsedTime(ms_out, e0, e1);
+            return e;
+        };
+        const float msv = (float)c->mat.Ms;
+        for (int pass = 0; pass < 3 && status == MM_OK; ++pass) {
+            float best_t = 0.f;
+            for (int v = 0; v < MM_TUNE_VARIANTS && status == MM_OK; ++v) {
+                float t = 0.f;
+                hipError_t e;
+                if (pass == 0)
+                    e = time_it([&] {
+                        hipError_t a = mmk::launch_xfwd(g, mz, nullptr, msv, S1, st, v);
+                        return a == hipSuccess ? mmk::launch_xinv(g, S1, H, st, v) : a;
+                    }, &t);
+                else if (pass == 1)
+                    e = time_it([&] {
+                        hipError_t a = mmk::launch_yfwd(g, S1, S2, st, v);
+                        return a == hipSuccess ? mmk::launch_yinv(g, S2, S1, st, v) : a;
+                    }, &t);
+                else
+                    e = time_it([&] { return mmk::launch_zconv(g, S2, K, false, st, v); }, &t);
+                if (e != hipSuccess) {
+                    status = hipcheck(c, e, "autotune timing");
+                    break;
+                }
+                if (v == 0 || t < best_t) {
+                    best_t = t;
+                    best[pass] = v;
+                }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (status != MM_OK) return status;
+        if (cache_path) {
+            if (FILE *f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%s %d %d %d %d %d %d\n", arch.c_str(), g.nx, g.ny, g.nz, best[0], best[1], best[2]);
+                std::fclose(f);
+            } else {
+                return fail(c, MM_EINVAL, "cannot append to the tuning cache %s", cache_path);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) c->tune[k] = best[k];
+    c->drop_graphs();
+    if (choice_out)
+        for (int k = 0; k < 3; ++k) choice_out[k] = best[k];
+    return MM_OK;
 }
 
 mm_status mm_set_compensated(mm_ctx *c, int on)

@@ -17,6 +17,8 @@
 // inverse transform yields H_demag directly.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "fft.hpp"
 #include "launch.hpp"
 
@@ -95,32 +97,45 @@ __host__ __device__ constexpr int nstages(int L, int E)
 }
 
 // ---- launch shapes (shared by kernels and launchers) ----------------------
-// y passes: one line of L per T = L/E threads, 256 threads per block
-template <int L>
+// Each pass has launch-shape variants V = 0 (the compile-time default), 1
+// and 2, chosen per geometry by mm_autotune / mm_set_tuning (single-sample
+// launches with L >= 64; batched launches and shorter lines use V = 0).
+// The x and y variants only regroup lines, so their results are identical
+// bit for bit; the z variants change the radix split (rounding only).
+constexpr int kVariants = 3;
+constexpr int kTuneMinL = 64;
+
+// y passes: one line of L per T = L/E threads, 256 threads per block;
+// V = 1 / 2: 2 / 4 lines per thread group (instead of MMK_Y_NC)
+template <int L, int V = 0>
 struct YShape {
     static constexpr int E = elems_per_thread(L), T = L / E;
-    static constexpr int NC = MMK_Y_NC;       // lines per thread group
+    static constexpr int NC = V == 0 ? MMK_Y_NC : (V == 1 ? 2 : 4);  // lines per thread group
     static constexpr int G = kThreads / T;    // thread groups per block
     static constexpr int LPB = G * NC;        // lines per block
     static constexpr int LDS = LPB * lds_line(L);
 };
-// z pass: CB columns of the three components per block
-template <int L>
+// z pass: CB columns of the three components per block; V = 1: the other
+// point count per thread (4 <-> 8), V = 2: half the columns
+template <int L, int V = 0>
 struct ZShape {
-    static constexpr int E0 = L >= 256 ? MMK_ZC_E_LONG : MMK_ZC_E;
+    static constexpr int Ed = L >= 256 ? MMK_ZC_E_LONG : MMK_ZC_E;
+    static constexpr int E0 = V == 1 ? (Ed == 4 ? 8 : 4) : Ed;
     static constexpr int E = L < E0 ? L : E0, T = L / E;
     static constexpr int KB = L >= 128 ? MMK_ZC_LDS_KB_LONG : MMK_ZC_LDS_KB;
     static constexpr int CBmax = cmax(1, (KB * 1024) / (3 * 8 * lds_line(L)));
-    static constexpr int CB = cmin(cmin(cmax(1, 1024 / T), pow2floor(CBmax)), L >= 128 ? MMK_ZC_CB_LONG : 1024);
+    static constexpr int CB0 = cmin(cmin(cmax(1, 1024 / T), pow2floor(CBmax)), L >= 128 ? MMK_ZC_CB_LONG : 1024);
+    static constexpr int CB = V == 2 ? cmax(1, CB0 / 2) : CB0;
     static constexpr int THREADS = T * CB;
     static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
 };
 // x passes: LPB lines of L = Px/2 complex per block (16 for 128-byte runs
-// in the transposed layout)
-template <int L>
+// in the transposed layout); V = 1 / 2: 8 / 32 lines
+template <int L, int V = 0>
 struct XShape {
     static constexpr int E = elems_per_thread(L), T = L / E;
-    static constexpr int LPB = cmax(1, cmin(64, cmin(MMK_X_LPB, 1024 / T)));
+    static constexpr int LPB0 = V == 0 ? MMK_X_LPB : (V == 1 ? 8 : 32);
+    static constexpr int LPB = cmax(1, cmin(64, cmin(LPB0, 1024 / T)));
     static constexpr int THREADS = T * LPB;
     static constexpr int LDS = LPB * lds_line(L) + L + 1;  // + twiddles exp(-2 pi i k/Px), k <= L
 };
@@ -140,10 +155,10 @@ __device__ __forceinline__ void load_half_twiddles(float2 *tw)
 // E[k] = (Z[k] + conj Z[L-k])/2, O[k] = (Z[k] - conj Z[L-k])/(2i).
 // The half spectrum kx in [0, L] is written transposed, S1[c][z][kx][y].
 // ------------------------------------------------------------------------
-template <int L, int NB>
-__global__ __launch_bounds__(XShape<L>::THREADS) void k_xfwd(Batch<XfwdDesc, NB> B)
+template <int L, int V, int NB>
+__global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xfwd(Batch<XfwdDesc, NB> B)
 {
-    using S = XShape<L>;
+    using S = XShape<L, V>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
     const XfwdDesc &D = B.s[blockIdx.z];
@@ -223,10 +238,10 @@ __device__ __forceinline__ long long s2_line(long long line, const Geo &g)
 // a2 / a4: FFT along y of contiguous columns (length Py, ny non-zeros in /
 // ny kept out), one column per T threads.
 // ------------------------------------------------------------------------
-template <int L, int NB>
+template <int L, int V, int NB>
 __global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
 {
-    using S = YShape<L>;
+    using S = YShape<L, V>;
     constexpr int E = S::E, T = S::T, NC = S::NC, LPB = S::LPB;
     extern __shared__ float2 sm[];
     const YDesc &D = B.s[blockIdx.z];
@@ -262,10 +277,10 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
     }
 }
 
-template <int L, int NB>
+template <int L, int V, int NB>
 __global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
 {
-    using S = YShape<L>;
+    using S = YShape<L, V>;
     constexpr int E = S::E, T = S::T, NC = S::NC, LPB = S::LPB;
     extern __shared__ float2 sm[];
     const YDesc &D = B.s[blockIdx.z];
@@ -346,10 +361,10 @@ __device__ __forceinline__ int zc_tile(int slot, int ntiles)
     return r < 8 ? lower : ntiles - 1 - lower;
 }
 
-template <int L, bool COMP, int NB>
-__global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B)
+template <int L, bool COMP, int V, int NB>
+__global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, NB> B)
 {
-    using S = ZShape<L>;
+    using S = ZShape<L, V>;
     constexpr int E = S::E, T = S::T, CB = S::CB;
     extern __shared__ float2 sm[];
     const ZDesc &D = B.s[blockIdx.z];
@@ -425,10 +440,10 @@ __global__ __launch_bounds__(ZShape<L>::THREADS) void k_zconv(Batch<ZDesc, NB> B
 // exp(+2 pi i k/Px); the unnormalised inverse length-L FFT of Z' is
 // x[2n] + i x[2n+1].
 // ------------------------------------------------------------------------
-template <int L, int NB>
-__global__ __launch_bounds__(XShape<L>::THREADS) void k_xinv(Batch<XinvDesc, NB> B)
+template <int L, int V, int NB>
+__global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(Batch<XinvDesc, NB> B)
 {
-    using S = XShape<L>;
+    using S = XShape<L, V>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
     const XinvDesc &D = B.s[blockIdx.z];
@@ -1294,17 +1309,45 @@ void clear_launch_events() { t_ev_start = t_ev_stop = nullptr; }
                        pack<DESC, kMaxBatch>(d, count));                                    \
     } while (0)
 
-hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s)
+// Runs go(integral_constant<int, V>) for the variant to use: `var` for a
+// single sample with L >= kTuneMinL, V = 0 otherwise.
+template <int LL, typename F>
+static void with_variant(int var, int count, F &&go)
 {
-    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if constexpr (LL >= kTuneMinL) {
+        if (count == 1 && var == 1) return go(std::integral_constant<int, 1>{});
+        if (count == 1 && var == 2) return go(std::integral_constant<int, 2>{});
+    }
+    go(std::integral_constant<int, 0>{});
+}
+
+// one launch of a pass kernel: KERNEL<ARGS..., V, NB>, NB = 1 for a single
+// sample, kMaxBatch (only with V = 0) for a batch
+#define MM_PASS_LAUNCH(KERNEL, DESC, GRID, BLOCK, LDS, STREAM, VV, ...)                        \
+    do {                                                                                    \
+        if (count == 1) {                                                                   \
+            MMK_LAUNCH((KERNEL<__VA_ARGS__, VV, 1>), GRID, BLOCK, LDS, STREAM, pack<DESC, 1>(d, count)); \
+        } else {                                                                            \
+            if constexpr (VV == 0)                                                          \
+                MMK_LAUNCH((KERNEL<__VA_ARGS__, 0, kMaxBatch>), GRID, BLOCK, LDS, STREAM,   \
+                           pack<DESC, kMaxBatch>(d, count));                                \
+        }                                                                                   \
+    } while (0)
+
+hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var)
+{
+    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
     const Extent e = extent(d, count);
     switch (d[0].g.Px / 2) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         if constexpr (LL <= 512) {                                                            \
-            using S = XShape<LL>;                                                             \
-            dim3 grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);                         \
-            MM_BATCH_LAUNCH(k_xfwd, XfwdDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, LL); \
+            with_variant<LL>(var, count, [&](auto vt) {                                       \
+                constexpr int VV = decltype(vt)::value;                                       \
+                using S = XShape<LL, VV>;                                                     \
+                dim3 grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);                     \
+                MM_PASS_LAUNCH(k_xfwd, XfwdDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, VV, LL); \
+            });                                                                               \
         }                                                                                     \
         break;                                                                                \
     }
@@ -1316,17 +1359,20 @@ hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s)
+hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
     const Extent e = extent(d, count);
     switch (d[0].g.Px / 2) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         if constexpr (LL <= 512) {                                                            \
-            using S = XShape<LL>;                                                             \
-            dim3 grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);                         \
-            MM_BATCH_LAUNCH(k_xinv, XinvDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, LL); \
+            with_variant<LL>(var, count, [&](auto vt) {                                       \
+                constexpr int VV = decltype(vt)::value;                                       \
+                using S = XShape<LL, VV>;                                                     \
+                dim3 grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);                     \
+                MM_PASS_LAUNCH(k_xinv, XinvDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, VV, LL); \
+            });                                                                               \
         }                                                                                     \
         break;                                                                                \
     }
@@ -1338,19 +1384,22 @@ hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s)
     return hipGetLastError();
 }
 
-static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t s)
+static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
     const Extent e = extent(d, count);
     switch (d[0].g.Py) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
-        using S = YShape<LL>;                                                                 \
-        dim3 grid((unsigned)((e.lines + S::LPB - 1) / S::LPB), 1, count);                    \
-        if (inverse)                                                                          \
-            MM_BATCH_LAUNCH(k_yinv, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, LL); \
-        else                                                                                  \
-            MM_BATCH_LAUNCH(k_yfwd, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, LL); \
+        with_variant<LL>(var, count, [&](auto vt) {                                           \
+            constexpr int VV = decltype(vt)::value;                                           \
+            using S = YShape<LL, VV>;                                                         \
+            dim3 grid((unsigned)((e.lines + S::LPB - 1) / S::LPB), 1, count);                \
+            if (inverse)                                                                      \
+                MM_PASS_LAUNCH(k_yinv, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, VV, LL); \
+            else                                                                              \
+                MM_PASS_LAUNCH(k_yfwd, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, VV, LL); \
+        });                                                                                   \
         break;                                                                                \
     }
         MM_LEN_CASES(CASE)
@@ -1361,23 +1410,27 @@ static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s) { return launch_y(d, count, false, s); }
-hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s) { return launch_y(d, count, true, s); }
+hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s, int var) { return launch_y(d, count, false, s, var); }
+hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s, int var) { return launch_y(d, count, true, s, var); }
 
-hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s)
+hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
+    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
     const Geo &g = d[0].g;
     switch (g.Pz) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
-        using S = ZShape<LL>;                                                                 \
-        dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, count);                                   \
-        const size_t lds = S::LDS * sizeof(float2);                                           \
-        if (comp)                                                                             \
-            MM_BATCH_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, LL, true);        \
-        else                                                                                  \
-            MM_BATCH_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, LL, false);       \
+        with_variant<LL>(comp ? 0 : var, count, [&](auto vt) {                                \
+            constexpr int VV = decltype(vt)::value;                                           \
+            using S = ZShape<LL, VV>;                                                         \
+            dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, count);                               \
+            const size_t lds = S::LDS * sizeof(float2);                                       \
+            if (comp) {                                                                       \
+                if constexpr (VV == 0) MM_PASS_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, 0, LL, true); \
+            } else {                                                                          \
+                MM_PASS_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, VV, LL, false); \
+            }                                                                                 \
+        });                                                                                   \
         break;                                                                                \
     }
         MM_LEN_CASES(CASE)
@@ -1421,30 +1474,31 @@ hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &
 }
 
 // ---- single-sample forms
-hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s)
+hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s,
+                       int var)
 {
     XfwdDesc d{g, m, ms_map, S1, ms};
-    return launch_xfwd(&d, 1, s);
+    return launch_xfwd(&d, 1, s, var);
 }
-hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s)
+hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s, int var)
 {
     YDesc d{g, S1, S2};
-    return launch_yfwd(&d, 1, s);
+    return launch_yfwd(&d, 1, s, var);
 }
-hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s)
+hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s, int var)
 {
     ZDesc d{g, S2, K};
-    return launch_zconv(&d, 1, comp, s);
+    return launch_zconv(&d, 1, comp, s, var);
 }
-hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s)
+hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s, int var)
 {
     YDesc d{g, S2, S1};
-    return launch_yinv(&d, 1, s);
+    return launch_yinv(&d, 1, s, var);
 }
-hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s)
+hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s, int var)
 {
     XinvDesc d{g, S1, Hd};
-    return launch_xinv(&d, 1, s);
+    return launch_xinv(&d, 1, s, var);
 }
 
 hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,

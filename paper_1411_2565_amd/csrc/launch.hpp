@@ -87,11 +87,14 @@ constexpr int kEnergyBlocks = 512;
 hipError_t init_tables(hipStream_t s);
 
 // demag pipeline, batched: `count` (1..kMaxBatch) samples sharing Px, Py, Pz
-hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s);
-hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s);
-hipError_t launch_zconv(const ZDesc *d, int count, bool compensated, hipStream_t s);
-hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s);
-hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s);
+// Pass launchers.  `var` selects a launch-shape variant (0 = default, 1, 2;
+// see the shape structs in kernels.hip) for single-sample launches with
+// lines of 64 points or more; other launches use 0.
+hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var = 0);
+hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s, int var = 0);
+hipError_t launch_zconv(const ZDesc *d, int count, bool compensated, hipStream_t s, int var = 0);
+hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s, int var = 0);
+hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var = 0);
 // local terms + Euler step (mode 1) or field output (mode 0), batched
 hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &p, uint32_t terms, int mode,
                               float dt, int renorm, int *flag, hipStream_t s);
@@ -104,11 +107,12 @@ bool launch_events_pending();
 void clear_launch_events();
 
 // single-sample forms
-hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s);
-hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s);
-hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool compensated, hipStream_t s);
-hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s);
-hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s);
+hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s,
+                       int var = 0);
+hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s, int var = 0);
+hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool compensated, hipStream_t s, int var = 0);
+hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s, int var = 0);
+hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s, int var = 0);
 
 // local terms: mode 0 writes H to out_h, mode 1 writes the Euler step to out_m
 hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
