@@ -544,7 +544,9 @@ __device__ __forceinline__ void vstore(float *p, const float (&o)[V])
     }
 }
 
-template <int MODE, int V, int NB>
+// MAPPED: the samples carry an Ms map (per-cell Ms, and vacuum where it is 0);
+// without one the kernel compiles to the uniform-Ms code alone.
+template <int MODE, int V, int NB, bool MAPPED>
 __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, LocalParams p, uint32_t terms,
                                                     float dt, int renorm, int *__restrict__ flag)
 {
@@ -552,7 +554,7 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     const Geo &g = D.g;
     const float *__restrict__ m = D.m;
     const float *__restrict__ Hd = D.Hd;
-    const float *__restrict__ ms_map = D.ms_map;
+    const float *__restrict__ ms_map = MAPPED ? D.ms_map : nullptr;
     const float *__restrict__ h_map = D.h_map;
     float *__restrict__ out_m = D.m_out;
     float *__restrict__ out_h = D.h_out;
@@ -578,7 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     // neighbours (a free surface), and their state never moves.
     float inv_ms[V];
     bool mag[V];
-    if (ms_map) {
+    if constexpr (MAPPED) {
         float s[V];
         vload<V>(ms_map + i0, s);
 #pragma unroll
@@ -600,8 +602,11 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
 #pragma unroll
             for (int j = 0; j < V; ++j) lap[c][j] = 0.f;
         // x neighbours: inside the vector, plus one scalar on each side
-        const bool has_l = x0 > 0 && (!ms_map || ms_map[i0 - 1] > 0.f);
-        const bool has_r = x0 + V < g.nx && (!ms_map || ms_map[i0 + V] > 0.f);
+        bool has_l = x0 > 0, has_r = x0 + V < g.nx;
+        if constexpr (MAPPED) {
+            has_l = has_l && ms_map[i0 - 1] > 0.f;
+            has_r = has_r && ms_map[i0 + V] > 0.f;
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const float left = has_l ? m[c * N + i0 - 1] : 0.f;
@@ -626,7 +631,7 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
         const long long sy = g.nx, sz = (long long)g.nx * g.ny;
         auto add = [&](long long off, float w) {
             bool nbm[V];
-            if (ms_map) {
+            if constexpr (MAPPED) {
                 float sn[V];
                 vload<V>(ms_map + i0 + off, sn);
 #pragma unroll
@@ -1453,14 +1458,25 @@ hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &
         items = it > items ? it : items;
     }
     dim3 grid((unsigned)((items + kThreads - 1) / kThreads), 1, count);
+    bool mapped = false;
+    for (int i = 0; i < count; ++i) mapped = mapped || d[i].ms_map != nullptr;
 #define LOCAL(MODE, V)                                                                        \
     do {                                                                                      \
-        if (count == 1)                                                                       \
-            MMK_LAUNCH((k_local<MODE, V, 1>), grid, dim3(kThreads), 0, s,             \
-                               pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);     \
-        else                                                                                  \
-            MMK_LAUNCH((k_local<MODE, V, kMaxBatch>), grid, dim3(kThreads), 0, s,     \
-                               pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
+        if (count == 1) {                                                                     \
+            if (mapped)                                                                       \
+                MMK_LAUNCH((k_local<MODE, V, 1, true>), grid, dim3(kThreads), 0, s,           \
+                           pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);         \
+            else                                                                              \
+                MMK_LAUNCH((k_local<MODE, V, 1, false>), grid, dim3(kThreads), 0, s,          \
+                           pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);         \
+        } else {                                                                              \
+            if (mapped)                                                                       \
+                MMK_LAUNCH((k_local<MODE, V, kMaxBatch, true>), grid, dim3(kThreads), 0, s,   \
+                           pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
+            else                                                                              \
+                MMK_LAUNCH((k_local<MODE, V, kMaxBatch, false>), grid, dim3(kThreads), 0, s,  \
+                           pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
+        }                                                                                     \
     } while (0)
     if (mode == 0) {
         if (vec) LOCAL(0, 4); else LOCAL(0, 1);
