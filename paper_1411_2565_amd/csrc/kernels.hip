@@ -1071,14 +1071,18 @@ __global__ __launch_bounds__(kThreads) void k_energy_final(int nblk, EnergyParam
 
 // ------------------------------------------------------------------------
 // a0: FP64 demag tensor.  N(o) between two cells o cells apart:
-//  near (all |o_a| <= 8): Newell's closed form, the second difference over
-//    the 27-point stencil of the auxiliary functions f (diagonal) and g
-//    (off-diagonal), divided by 4 pi V;
+//  near (every |o_a| d_a <= 8 max(dx, dy, dz)): Newell's closed form, the
+//    second difference over the 27-point stencil of the auxiliary functions
+//    f (diagonal) and g (off-diagonal), divided by 4 pi V;
 //  far: (1/V) integral over s in [-d,d]^3 of the dipole kernel
 //    K(r) = (I/r^3 - 3 r r^T/r^5)/(4 pi) at r = o d + s, weighted by
 //    prod (d_a - |s_a|); each half-axis with 4-point Gauss-Legendre.
+// The split is in lengths, not cells: with flat cells (say 5 x 5 x 1 nm) an
+// offset of 9 cells along the thin axis is under two cell widths away, where
+// 4 nodes are accurate to ~1e-7 only, while Newell's form holds to ~1e-12
+// out to 8 of the largest cell dimension.
 // ------------------------------------------------------------------------
-constexpr int kNearCells = 8;
+constexpr double kNearWidths = 8.0;
 
 __device__ double nf(double x, double y, double z)
 {
@@ -1145,7 +1149,8 @@ __global__ __launch_bounds__(kThreads) void k_tensor_octant(Geo g, double dx, do
     const int oy = (int)(r % g.ny), oz = (int)(r / g.ny);
     const double X = ox * dx, Y = oy * dy, Z = oz * dz;
     double v[6];
-    if (ox <= kNearCells && oy <= kNearCells && oz <= kNearCells) {
+    const double reach = kNearWidths * fmax(dx, fmax(dy, dz)) * (1.0 + 1e-12);
+    if (X <= reach && Y <= reach && Z <= reach) {
         v[0] = newell27<false>(X, Y, Z, dx, dy, dz);
         v[1] = newell27<false>(Y, X, Z, dy, dx, dz);
         v[2] = newell27<false>(Z, Y, X, dz, dy, dx);

@@ -44,6 +44,8 @@ GEOMS = [
     ((2, 3, 4), (5e-9,) * 3),              # smallest x
     ((64, 20, 2), (4e-9, 4e-9, 3e-9)),     # several FFT tiles along x
     ((40, 24, 6), (3e-9, 4e-9, 5e-9)),     # anisotropic cells
+    ((2, 512, 2), (5e-9, 2e-9, 5e-9)),     # longest y transform (1024 points)
+    ((3, 2, 512), (5e-9, 5e-9, 1e-9)),     # longest z transform (1024 points)
 ]
 
 
@@ -243,6 +245,30 @@ def test_block_256x256x32_sampled_observers(gpu_lib):
     e = rel(Hd[:, obs], Ho)
     print(f"block 256x256x32 sampled demag: rel L2 {e:.2e}")
     assert e < 1e-5
+
+
+def test_block_256x256x32_sampled_step(gpu_lib):
+    """The benchmark's launch configuration (one eager mm_step_llg of the
+    256x256x32 block): the step increment m1 - m0 at 512 sampled cells
+    against the oracle's full Euler step there (direct-sum demag over all
+    sources, exchange, LLG, renormalisation)."""
+    w = workloads.BLOCK_256x256x32
+    m0, _ = workloads.inputs(w)
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    m = gpu(m0)
+    mf = host(m)
+    sim.step(m, 1, w.dt)
+    sim.sync()
+    rng = np.random.default_rng(321)
+    N = w.N
+    obs = np.unique(np.concatenate([[0, 255, N - 256, N - 1], rng.choice(N, 512, replace=False)]))
+    P = oracle.Problem(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    m1o = P.step_cells(mf, obs, w.dt)
+    m0s = mf.reshape(3, -1)[:, obs]
+    e = rel(host(m).reshape(3, -1)[:, obs] - m0s, m1o - m0s)
+    print(f"block 256x256x32 one step at {obs.size} cells: increment rel L2 {e:.2e}")
+    assert e < 1e-5
+    sim.close()
 
 
 def test_invalid_arguments(gpu_lib):
