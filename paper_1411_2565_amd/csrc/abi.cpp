@@ -1090,6 +1090,43 @@ mmk::LocalParams batch_params(const mm_batch *b)
 }
 
 // enqueue nsteps steps of every sample (no checks)
+// Launch lists of one batched step: each pass depends only on its own
+// transform length (x on Px, y on Py, z on Pz), so samples are grouped per
+// pass by that length alone, in chunks of up to kMaxBatch, rather than by
+// their whole padded size; the local pass takes any mix (chunks split by
+// whether nx is a multiple of 4, for its vector width).
+struct BatchPlan {
+    std::vector<std::vector<int>> x, y, z, loc;
+    std::vector<const float *> K;  // tensor spectrum of each sample's padded size
+};
+
+BatchPlan batch_plan(mm_batch *b)
+{
+    BatchPlan pl;
+    const int ns = (int)b->samples.size();
+    pl.K.assign(ns, nullptr);
+    for (const auto &gr : b->groups)
+        for (int i : gr.members) pl.K[i] = b->at<float>(gr.o_K);
+    auto split = [&](auto key, std::vector<std::vector<int>> &out) {
+        std::vector<std::pair<long long, int>> keyed;
+        for (int i = 0; i < ns; ++i) keyed.push_back({key(b->samples[i].g), i});
+        std::stable_sort(keyed.begin(), keyed.end(),
+                         [](const auto &u, const auto &v) { return u.first < v.first; });
+        for (size_t k = 0; k < keyed.size();) {
+            std::vector<int> chunk;
+            const long long kk = keyed[k].first;
+            while (k < keyed.size() && keyed[k].first == kk && (int)chunk.size() < mmk::kMaxBatch)
+                chunk.push_back(keyed[k++].second);
+            out.push_back(chunk);
+        }
+    };
+    split([](const mmk::Geo &g) { return (long long)g.Px; }, pl.x);
+    split([](const mmk::Geo &g) { return (long long)g.Py; }, pl.y);
+    split([](const mmk::Geo &g) { return (long long)g.Pz; }, pl.z);
+    split([](const mmk::Geo &g) { return (long long)(g.nx % 4 == 0); }, pl.loc);
+    return pl;
+}
+
 mm_status batch_enqueue(mm_batch *b, float *m, int64_t nsteps, double dt, uint32_t flags)
 {
     const mmk::LocalParams p = batch_params(b);
@@ -1097,39 +1134,69 @@ mm_status batch_enqueue(mm_batch *b, float *m, int64_t nsteps, double dt, uint32
     const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
     int *flag = b->at<int>(b->o_flag);
     hipStream_t st = b->stream;
+    const BatchPlan pl = batch_plan(b);
     std::vector<mmk::XfwdDesc> xf;
-    std::vector<mmk::YDesc> yf, yi;
+    std::vector<mmk::YDesc> yd;
     std::vector<mmk::ZDesc> zc;
     std::vector<mmk::XinvDesc> xi;
     std::vector<mmk::LocalDesc> lc;
     for (int64_t s = 0; s < nsteps; ++s) {
-        for (const auto &gr : b->groups) {
-            for (size_t k0 = 0; k0 < gr.members.size(); k0 += mmk::kMaxBatch) {
-                const int cnt = (int)std::min<size_t>(mmk::kMaxBatch, gr.members.size() - k0);
-                xf.clear(); yf.clear(); yi.clear(); zc.clear(); xi.clear(); lc.clear();
-                for (int k = 0; k < cnt; ++k) {
-                    const auto &sm = b->samples[gr.members[k0 + k]];
-                    float *mb[2] = {m + sm.m_off, b->at<float>(sm.o_mt)};
-                    const float *src = mb[s & 1];
-                    float *dst = mb[(s + 1) & 1];
-                    float2 *S1 = b->at<float2>(sm.o_S1), *S2 = b->at<float2>(sm.o_S2);
-                    float *Hd = b->at<float>(sm.o_S2);
-                    xf.push_back({sm.g, src, nullptr, S1, (float)b->mat.Ms});
-                    yf.push_back({sm.g, S1, S2});
-                    zc.push_back({sm.g, S2, b->at<float>(gr.o_K)});
-                    yi.push_back({sm.g, S2, S1});
-                    xi.push_back({sm.g, S1, Hd});
-                    lc.push_back({sm.g, src, Hd, nullptr, nullptr, dst, nullptr, (float)sm.h[0], (float)sm.h[1],
-                                  (float)sm.h[2]});
-                }
-                MM_TRY(bhip(b, mmk::launch_xfwd(xf.data(), cnt, st), "batch xfwd"));
-                MM_TRY(bhip(b, mmk::launch_yfwd(yf.data(), cnt, st), "batch yfwd"));
-                MM_TRY(bhip(b, mmk::launch_zconv(zc.data(), cnt, comp, st), "batch zconv"));
-                MM_TRY(bhip(b, mmk::launch_yinv(yi.data(), cnt, st), "batch yinv"));
-                MM_TRY(bhip(b, mmk::launch_xinv(xi.data(), cnt, st), "batch xinv"));
-                MM_TRY(bhip(b, mmk::launch_local_batch(lc.data(), cnt, p, MM_T_ALL, 1, (float)dt, renorm, flag, st),
-                            "batch local"));
+        auto src_of = [&](const mm_batch::Sample &sm) -> const float * {
+            return (s & 1) ? b->at<float>(sm.o_mt) : m + sm.m_off;
+        };
+        auto dst_of = [&](const mm_batch::Sample &sm) -> float * {
+            return (s & 1) ? m + sm.m_off : b->at<float>(sm.o_mt);
+        };
+        for (const auto &ch : pl.x) {
+            xf.clear();
+            for (int i : ch) {
+                const auto &sm = b->samples[i];
+                xf.push_back({sm.g, src_of(sm), nullptr, b->at<float2>(sm.o_S1), (float)b->mat.Ms});
             }
+            MM_TRY(bhip(b, mmk::launch_xfwd(xf.data(), (int)ch.size(), st), "batch xfwd"));
+        }
+        for (const auto &ch : pl.y) {
+            yd.clear();
+            for (int i : ch) {
+                const auto &sm = b->samples[i];
+                yd.push_back({sm.g, b->at<float2>(sm.o_S1), b->at<float2>(sm.o_S2)});
+            }
+            MM_TRY(bhip(b, mmk::launch_yfwd(yd.data(), (int)ch.size(), st), "batch yfwd"));
+        }
+        for (const auto &ch : pl.z) {
+            zc.clear();
+            for (int i : ch) {
+                const auto &sm = b->samples[i];
+                zc.push_back({sm.g, b->at<float2>(sm.o_S2), pl.K[i]});
+            }
+            MM_TRY(bhip(b, mmk::launch_zconv(zc.data(), (int)ch.size(), comp, st), "batch zconv"));
+        }
+        for (const auto &ch : pl.y) {
+            yd.clear();
+            for (int i : ch) {
+                const auto &sm = b->samples[i];
+                yd.push_back({sm.g, b->at<float2>(sm.o_S2), b->at<float2>(sm.o_S1)});
+            }
+            MM_TRY(bhip(b, mmk::launch_yinv(yd.data(), (int)ch.size(), st), "batch yinv"));
+        }
+        for (const auto &ch : pl.x) {
+            xi.clear();
+            for (int i : ch) {
+                const auto &sm = b->samples[i];
+                xi.push_back({sm.g, b->at<float2>(sm.o_S1), b->at<float>(sm.o_S2)});
+            }
+            MM_TRY(bhip(b, mmk::launch_xinv(xi.data(), (int)ch.size(), st), "batch xinv"));
+        }
+        for (const auto &ch : pl.loc) {
+            lc.clear();
+            for (int i : ch) {
+                const auto &sm = b->samples[i];
+                lc.push_back({sm.g, src_of(sm), b->at<float>(sm.o_S2), nullptr, nullptr, dst_of(sm), nullptr,
+                              (float)sm.h[0], (float)sm.h[1], (float)sm.h[2]});
+            }
+            MM_TRY(bhip(b, mmk::launch_local_batch(lc.data(), (int)ch.size(), p, MM_T_ALL, 1, (float)dt, renorm,
+                                                   flag, st),
+                        "batch local"));
         }
     }
     if (nsteps & 1)

@@ -373,7 +373,11 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, 
     const float *__restrict__ K = D.K;
     const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
     const int kx = blockIdx.y;
-    const int ky = zc_tile(blockIdx.x, gridDim.x) * CB + col;
+    const int tile = zc_tile(blockIdx.x, gridDim.x);
+    // a batch launch covers the largest sample: whole tiles beyond this one
+    // leave (block-uniform, before any barrier)
+    if (kx >= g.Hx || tile * CB >= g.Py) return;
+    const int ky = tile * CB + col;
     const bool ok = ky < g.Py;
     const long long zs = g.Py;                                // stride between z
     const long long cs = (long long)g.Hx * g.nz * g.Py;       // between components
@@ -1262,7 +1266,7 @@ static Batch<Dsc, NB> pack(const Dsc *d, int count)
 
 // grid extents over a batch of samples with a common padded size
 struct Extent {
-    int ny = 0, nz = 0;
+    int ny = 0, nz = 0, Py = 0, Hx = 0;
     long long lines = 0, items = 0;
 };
 template <typename Dsc>
@@ -1273,6 +1277,8 @@ static Extent extent(const Dsc *d, int count)
         const Geo &g = d[i].g;
         e.ny = g.ny > e.ny ? g.ny : e.ny;
         e.nz = g.nz > e.nz ? g.nz : e.nz;
+        e.Py = g.Py > e.Py ? g.Py : e.Py;
+        e.Hx = g.Hx > e.Hx ? g.Hx : e.Hx;
         const long long l = 3LL * g.nz * g.Hx;
         e.lines = l > e.lines ? l : e.lines;
         const long long it = (g.nx % 4 == 0) ? g.N / 4 : g.N;
@@ -1344,9 +1350,18 @@ static void with_variant(int var, int count, F &&go)
         }                                                                                   \
     } while (0)
 
+template <typename Dsc>
+static bool same_px(const Dsc *d, int count)
+{
+    for (int i = 1; i < count; ++i)
+        if (d[i].g.Px != d[0].g.Px) return false;
+    return true;
+}
+
 hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
+    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants || !same_px(d, count))
+        return hipErrorInvalidValue;
     const Extent e = extent(d, count);
     switch (d[0].g.Px / 2) {
 #define CASE(LL)                                                                              \
@@ -1371,7 +1386,8 @@ hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var)
 
 hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
+    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants || !same_px(d, count))
+        return hipErrorInvalidValue;
     const Extent e = extent(d, count);
     switch (d[0].g.Px / 2) {
 #define CASE(LL)                                                                              \
@@ -1397,6 +1413,8 @@ hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var)
 static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t s, int var)
 {
     if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
+    for (int i = 1; i < count; ++i)
+        if (d[i].g.Py != d[0].g.Py) return hipErrorInvalidValue;
     const Extent e = extent(d, count);
     switch (d[0].g.Py) {
 #define CASE(LL)                                                                              \
@@ -1427,13 +1445,16 @@ hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s, int
 {
     if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
     const Geo &g = d[0].g;
+    const Extent e = extent(d, count);  // samples may differ in Py and Hx, not in Pz
+    for (int i = 1; i < count; ++i)
+        if (d[i].g.Pz != g.Pz) return hipErrorInvalidValue;
     switch (g.Pz) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         with_variant<LL>(comp ? 0 : var, count, [&](auto vt) {                                \
             constexpr int VV = decltype(vt)::value;                                           \
             using S = ZShape<LL, VV>;                                                         \
-            dim3 grid((g.Py + S::CB - 1) / S::CB, g.Hx, count);                               \
+            dim3 grid((e.Py + S::CB - 1) / S::CB, e.Hx, count);                               \
             const size_t lds = S::LDS * sizeof(float2);                                       \
             if (comp) {                                                                       \
                 if constexpr (VV == 0) MM_PASS_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, 0, LL, true); \
