@@ -31,11 +31,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel sources whose SHA-256 is
 # recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv<64, false, 0, 1>: FETCH_SIZE 76 678.1 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258093261,
-              "source_sha": "68992c30fd1eecfe61c969dbc0f576bfb24a22fe82b7e79a7d39754bacf68142"},
+    # k_zconv<64, false, 0, 1>: FETCH_SIZE 76 681.6 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258100429,
+              "source_sha": "d0cb09a78390786e9c581bbd2674308906d4003d8469415d26074a79422cdf02"},
 }
-
 
 def kernel_source_sha():
     import hashlib
@@ -130,6 +129,25 @@ def cpu_baseline(w, m0, target_s=12.0):
                        f"exchange/anisotropy/Zeeman + LLG) at {ncell} randomly sampled cells of the "
                        f"{w.n[0]}x{w.n[1]}x{w.n[2]} block; {el:.1f} s; tensor table build "
                        f"{t_tab:.1f} s not counted")}
+
+
+def cpu_full_steps():
+    """The FP64 oracle's full Euler step (direct sum over all sources) on
+    the three workloads small enough for it: seconds per step and
+    cell-steps/s, timed on the host threads."""
+    import oracle
+    from paper_1411_2565_amd import workloads
+    rows = []
+    for w in (workloads.BLOCK_16x16x2, workloads.BLOCK_64x64x8, workloads.FILM_128x128x4):
+        m0, h = workloads.inputs(w)
+        P = oracle.Problem(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=h)
+        reps = 20 if w.N <= 1024 else 1
+        t = time.perf_counter()
+        P.run(m0, reps, w.dt)
+        el = (time.perf_counter() - t) / reps
+        rows.append({"workload": w.name, "cells": w.N, "s_per_step": float(f"{el:.4g}"),
+                     "cell_steps_per_s": w.N / el})
+    return {"kind": "oracle", "cores": oracle.threads(), "rows": rows}
 
 
 def adjoint_ratio(binding, T=2000):
@@ -483,10 +501,11 @@ def main():
         print("bench: non-regular geometry", file=sys.stderr, flush=True)
         geo = geometry_rate(binding)
 
-    cpu = None
+    cpu = cpu_full = None
     if not args.no_cpu:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         cpu = cpu_baseline(w, m0)
+        cpu_full = cpu_full_steps()
 
     line = {
         "metric": "cell-steps/s (H_eff+LLG) at 256x256x32 FP32, %HBM peak; adjoint/fwd time ratio",
@@ -507,6 +526,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)},
         "cpu_baseline": cpu,
+        "cpu_full_steps": cpu_full,
         "step_bytes": step_bytes,
         "copy_GBps": copy_bw,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
