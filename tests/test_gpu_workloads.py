@@ -153,3 +153,32 @@ def test_sp4_crop_reversal_fields(gpu_lib):
     ed = rel(dg, do)
     print(f"SP4 crop field 1 - field 2: |diff| {np.linalg.norm(do):.3e}, rel L2 of the difference {ed:.2e}")
     assert ed < 3e-2  # FP32 state rounding alone is ~3e-3 of this difference
+
+
+@pytest.mark.parametrize("n", [(512, 384, 256), (512, 512, 512)])
+def test_maximum_size_uniform_body_average(gpu_lib, n):
+    """The largest grids the library accepts (every axis up to 512 cells,
+    FFTs of 1024): uniform magnetisation along each axis in turn gives a
+    volume-averaged demag field of -D Ms, D the whole box's demag factor
+    (Aharoni's closed form; 1/3 for the cube).  The cell-averaged tensor
+    summed over all cell pairs reproduces D exactly, so only FP32 rounding
+    and the far-field quadrature separate the two."""
+    import torch
+    from tests.closed_forms import aharoni
+    d = 5e-9
+    Ms = 8e5
+    D = aharoni(n[0] * d, n[1] * d, n[2] * d)
+    sim = gpu_lib.Sim(n, (d,) * 3, Ms=Ms, A=1.3e-11)
+    m = torch.zeros((3, n[2], n[1], n[0]), dtype=torch.float32, device="cuda:0")
+    for axis in range(3):
+        m.zero_()
+        m[axis] = 1.0
+        H = sim.heff(m, gpu_lib.MM_T_DEMAG)
+        avg = H.double().mean(dim=(1, 2, 3)).cpu().numpy()
+        del H
+        print(f"box {n}, m along {axis}: <H>/Ms = {avg / Ms}, -D = {-D[axis]:.9f}")
+        assert abs(avg[axis] + D[axis] * Ms) < 2e-6 * Ms
+        assert np.abs(np.delete(avg, axis)).max() < 2e-6 * Ms
+    sim.close()
+    del m
+    torch.cuda.empty_cache()
