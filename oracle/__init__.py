@@ -206,7 +206,7 @@ class Problem:
                       _p(tr) if traj else ctypes.cast(None, _D))
         return (m, tr) if traj else m
 
-    PAIRS = {"heun_euler": 1, "bs23": 2}
+    PAIRS = {"heun_euler": 1, "bs23": 2, "dp54": 3}
 
     def run_adaptive(self, m0, t_end, dt0, tol, pair="heun_euler", max_steps=10**6):
         """Adaptive steps with an embedded pair up to time t_end: returns

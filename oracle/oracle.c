@@ -677,13 +677,15 @@ int orc_run_rk(const orc_problem *p, double *m, int64_t nsteps, double dt, int m
 /*   pair 2, Bogacki-Shampine, order 3(2):                                   */
 /*     A[1][0] = 1/2, A[2][1] = 3/4;  b = (2/9, 1/3, 4/9, 0);                */
 /*     bh = (7/24, 1/4, 1/3, 1/8), the fourth stage evaluated at m'          */
+/*   pair 3, Dormand-Prince, order 5(4), seven stages, the seventh at m'     */
+/*     (the published 1980 tableau, written out below).                      */
 /* Returns 0, or -1 for an unknown pair, -2 when max_steps attempts do not   */
 /* reach t_end.                                                              */
 /* ------------------------------------------------------------------------ */
 int orc_run_adaptive(const orc_problem *p, double *m, double t_end, double *dt_io, double tol, int pair,
                      int64_t max_steps, int64_t *accepted, int64_t *rejected)
 {
-    double A[4][4] = {{0}}, b[4] = {0}, bh[4] = {0};
+    double A[7][7] = {{0}}, b[7] = {0}, bh[7] = {0};
     int s, q;
     if (pair == 1) {
         s = 2; q = 1;
@@ -695,11 +697,24 @@ int orc_run_adaptive(const orc_problem *p, double *m, double t_end, double *dt_i
         A[1][0] = 0.5; A[2][1] = 0.75;
         b[0] = 2.0 / 9.0; b[1] = 1.0 / 3.0; b[2] = 4.0 / 9.0;
         bh[0] = 7.0 / 24.0; bh[1] = 0.25; bh[2] = 1.0 / 3.0; bh[3] = 0.125;
+    } else if (pair == 3) {
+        s = 7; q = 4;
+        A[1][0] = 1.0 / 5.0;
+        A[2][0] = 3.0 / 40.0; A[2][1] = 9.0 / 40.0;
+        A[3][0] = 44.0 / 45.0; A[3][1] = -56.0 / 15.0; A[3][2] = 32.0 / 9.0;
+        A[4][0] = 19372.0 / 6561.0; A[4][1] = -25360.0 / 2187.0; A[4][2] = 64448.0 / 6561.0;
+        A[4][3] = -212.0 / 729.0;
+        A[5][0] = 9017.0 / 3168.0; A[5][1] = -355.0 / 33.0; A[5][2] = 46732.0 / 5247.0;
+        A[5][3] = 49.0 / 176.0; A[5][4] = -5103.0 / 18656.0;
+        b[0] = 35.0 / 384.0; b[2] = 500.0 / 1113.0; b[3] = 125.0 / 192.0;
+        b[4] = -2187.0 / 6784.0; b[5] = 11.0 / 84.0;
+        bh[0] = 5179.0 / 57600.0; bh[2] = 7571.0 / 16695.0; bh[3] = 393.0 / 640.0;
+        bh[4] = -92097.0 / 339200.0; bh[5] = 187.0 / 2100.0; bh[6] = 1.0 / 40.0;
     } else {
         return -1;
     }
-    /* pair 2: stages 0-2 build m', stage 3 is f(m') */
-    const int sres = pair == 2 ? 3 : s;
+    /* pairs 2 and 3: the stages before the last build m', the last is f(m') */
+    const int sres = pair >= 2 ? s - 1 : s;
     const size_t N = (size_t)p->nx * p->ny * p->nz;
     double *k = (double *)malloc(sizeof(double) * 3 * N * s);
     double *mi = (double *)malloc(sizeof(double) * 3 * N);
@@ -727,9 +742,9 @@ int orc_run_adaptive(const orc_problem *p, double *m, double t_end, double *dt_i
             mn[e] = m[e] + h * a;
         }
         renormalise(p, mn, N);
-        if (pair == 2) {
+        if (pair >= 2) {
             orc_heff(p, mn, p->terms, H);
-            orc_llg_rhs(p, mn, H, k + (size_t)3 * 3 * N);
+            orc_llg_rhs(p, mn, H, k + (size_t)(s - 1) * 3 * N);
         }
         double err = 0.0;
         for (size_t i = 0; i < N; ++i) {

@@ -342,24 +342,30 @@ def test_runge_kutta_methods_integrate_the_same_equation():
     scale = np.linalg.norm(rk4 - m)
     assert np.linalg.norm(heun - rk4) < 1e-5 * scale
     assert np.linalg.norm(euler - rk4) < 5e-3 * scale
+    for pair in ("heun_euler", "bs23", "dp54"):  # adaptive pairs at a tight tolerance
+        ma = P.run_adaptive(m, T, 1e-14, 1e-8, pair)[0]
+        assert np.linalg.norm(ma - rk4) < 1e-6 * scale, pair
 
 
-def _macrospin_setup():
-    alpha, Hz, T = 0.1, 1e5, 0.2e-9
+def _macrospin_setup(T=0.2e-9):
+    alpha, Hz = 0.1, 1e5
     th0, ph0 = 1.0, 0.3
     m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(3, 1, 1, 1)
     P = oracle.Problem((1, 1, 1), (5e-9,) * 3, alpha=alpha, hext=(0, 0, Hz), terms=oracle.T_ZEEMAN)
     return P, m0, T, macrospin(th0, ph0, Hz, alpha, 2.211e5, T)
 
 
-@pytest.mark.parametrize("pair,steps_ratio", [("heun_euler", 10.0), ("bs23", 100.0 ** (1 / 3))])
-def test_adaptive_pairs_scale_with_tolerance(pair, steps_ratio):
+@pytest.mark.parametrize("pair,T,steps_ratio", [("heun_euler", 0.2e-9, 10.0),
+                                                ("bs23", 0.2e-9, 100.0 ** (1 / 3)),
+                                                ("dp54", 1e-9, 100.0 ** (1 / 5))])
+def test_adaptive_pairs_scale_with_tolerance(pair, T, steps_ratio):
     """Adaptive steps on the exact macrospin solution: the global error is
     proportional to the tolerance, and the number of accepted steps grows as
     tol^(-1/(q+1)) (q the lower order: 1 for Heun/Euler, 2 for
-    Bogacki-Shampine).  A wrong weight in either member of the pair changes
+    Bogacki-Shampine, 4 for Dormand-Prince, whose few large steps need the
+    longer horizon).  A wrong weight in either member of the pair changes
     one of the two exponents."""
-    P, m0, T, exact = _macrospin_setup()
+    P, m0, T, exact = _macrospin_setup(T)
     res = {tol: P.run_adaptive(m0, T, 1e-13, tol, pair) for tol in (1e-5, 1e-7)}
     err = {tol: np.linalg.norm(r[0].ravel() - exact) for tol, r in res.items()}
     assert 70 < err[1e-5] / err[1e-7] < 140, err
