@@ -317,8 +317,8 @@ def sp4_rate(binding, steps=2048):
 def integrator_rates(binding, steps=200):
     """Per-step time of the Euler, Heun and classic RK4 steps on the
     256x256x32 block (1, 2 and 4 field evaluations per step), eager, and of
-    adaptive Bogacki-Shampine 3(2) attempts (4 evaluations, an error
-    reduction and a host round trip each)."""
+    adaptive Bogacki-Shampine 3(2) and Dormand-Prince 5(4) attempts (4 and
+    7 evaluations, an error reduction and a host round trip each)."""
     import torch
     from paper_1411_2565_amd import workloads
     w = workloads.BLOCK_256x256x32
@@ -337,6 +337,12 @@ def integrator_rates(binding, steps=200):
     dt, acc, rej = sim.run_adaptive(m, 2e-12, 1e-14, 1e-5, binding.MM_F_BS23)
     el = time.perf_counter() - t0
     out["bs23_adaptive"] = {"t_end": 2e-12, "tol": 1e-5, "accepted": acc, "rejected": rej,
+                            "last_dt": dt, "us_per_attempt": round(1e6 * el / max(acc + rej, 1), 1)}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dt, acc, rej = sim.run_adaptive(m, 2e-12, 1e-14, 1e-5, binding.MM_F_DP54)
+    el = time.perf_counter() - t0
+    out["dp54_adaptive"] = {"t_end": 2e-12, "tol": 1e-5, "accepted": acc, "rejected": rej,
                             "last_dt": dt, "us_per_attempt": round(1e6 * el / max(acc + rej, 1), 1)}
     sim.sync()
     sim.close()

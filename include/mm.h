@@ -81,7 +81,8 @@ enum {
     MM_F_GRAPH = 4,        /* mm_step_llg: replay captured chunks of 32 steps (needs a non-null stream) */
     MM_F_HEUN = 8,         /* mm_step_llg: Heun step (explicit trapezoid, order 2) instead of Euler */
     MM_F_RK4 = 16,         /* mm_step_llg: classic fourth-order Runge-Kutta step instead of Euler */
-    MM_F_BS23 = 32         /* mm_step_adaptive: Bogacki-Shampine 3(2) pair (MM_F_HEUN: Heun/Euler 2(1)) */
+    MM_F_BS23 = 32,        /* mm_step_adaptive: Bogacki-Shampine 3(2) pair (MM_F_HEUN: Heun/Euler 2(1)) */
+    MM_F_DP54 = 64         /* mm_step_adaptive: Dormand-Prince 5(4) pair */
 };
 
 /* Create a context for a geometry on HIP device `device`; work is enqueued
@@ -217,12 +218,14 @@ mm_status mm_autotune(mm_ctx *c, const char *cache_path, int32_t choice_out[3]);
  *              bh = (1, 0);
  *   MM_F_BS23  Bogacki-Shampine 3(2): a = (1/2, 3/4), b = (2/9, 1/3, 4/9),
  *              a fourth stage at the new state, bh = (7/24, 1/4, 1/3, 1/8);
+ *   MM_F_DP54  Dormand-Prince 5(4), the published seven-stage tableau, the
+ *              seventh stage at the new state (q = 4);
  * plus optionally MM_F_NO_RENORM and MM_F_COMPENSATED.  Stage states and the
  * result are renormalised as in mm_step_llg.  Each attempt with step h
  * estimates err = max over cells |h sum_i (b_i - bh_i) k_i| (FP32, reduced
  * on the GPU) and is accepted when err <= tol (tol dimensionless, in units
  * of |m|).  Either way the next step is
- *   h * min(5, max(0.2, 0.9 (tol/err)^(1/(q+1))))   (q = 1 or 2; 5 if err = 0)
+ *   h * min(5, max(0.2, 0.9 (tol/err)^(1/(q+1))))   (q = 1, 2 or 4; 5 if err = 0)
  * and a step that would pass t_end is shortened to end there.  *dt_io gives
  * the first step and receives the last proposed one; *accepted / *rejected
  * (may be NULL) count the attempts.  The host waits for the GPU after every

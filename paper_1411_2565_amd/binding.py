@@ -15,7 +15,7 @@ from . import build as _build
 
 MM_OK, MM_EINVAL, MM_ESTATE, MM_ENOMEM, MM_EHIP, MM_EUNSUP, MM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MM_T_EXCH, MM_T_DEMAG, MM_T_ANIS, MM_T_ZEEMAN, MM_T_ALL = 1, 2, 4, 8, 15
-MM_F_NO_RENORM, MM_F_COMPENSATED, MM_F_GRAPH, MM_F_HEUN, MM_F_RK4, MM_F_BS23 = 1, 2, 4, 8, 16, 32
+MM_F_NO_RENORM, MM_F_COMPENSATED, MM_F_GRAPH, MM_F_HEUN, MM_F_RK4, MM_F_BS23, MM_F_DP54 = 1, 2, 4, 8, 16, 32, 64
 
 _NAMES = {0: "MM_OK", -1: "MM_EINVAL", -2: "MM_ESTATE", -3: "MM_ENOMEM", -4: "MM_EHIP",
           -5: "MM_EUNSUP", -6: "MM_ENONFINITE"}

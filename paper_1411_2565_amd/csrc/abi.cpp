@@ -165,7 +165,8 @@ void layout(mm_ctx *c)
     c->o_S1 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.ny);
     c->o_S2 = st.take(sizeof(float2) * 3 * (size_t)g.nz * g.Hx * g.Py);
     c->o_mtmp = st.take(sizeof(float) * 3 * N);
-    c->o_rk = st.take(sizeof(float) * 12 * N);  // Runge-Kutta: two stage states, accumulator, error accumulator
+    // Runge-Kutta: two stage states, accumulator, error accumulator, four stored slopes
+    c->o_rk = st.take(sizeof(float) * 24 * N);
     Carve tb;
     tb.off = region;
     c->o_T = tb.take(sizeof(double) * 6 * N);
@@ -253,6 +254,8 @@ mmk::LocalParams local_params(const mm_ctx *c)
     const double c1 = -m.gamma0 / (1.0 + m.alpha * m.alpha);
     p.c1 = (float)c1;
     p.c2 = (float)(m.alpha * c1);
+    p.stage_kstore = -1;  // no stored slopes unless a tableau asks for them
+    p.stage_nprev = 0;
     return p;
 }
 
@@ -534,7 +537,7 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
                 float *out = p.stage_last ? dst(s) : stage[i & 1];
                 MM_TRY(timed(c, MM_K_LOCAL, "runge-kutta stage", [&] {
                     return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, nullptr,
-                                             (float)dt, renorm, out, flag, c->stream);
+                                             nullptr, (float)dt, renorm, out, flag, c->stream);
                 }));
                 eval = out;
             }
@@ -554,11 +557,16 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
 
 // One attempted step of an embedded pair from `base` to `out` with step h;
 // the stream is synchronised and *err receives max over cells of the local
-// error estimate |dt sum_i (b_i - bh_i) k_i|.
+// error estimate |h sum_i (b_i - bh_i) k_i|.
 //   2(1) Heun / Euler:      a = (1), b = (1/2, 1/2), bh = (1, 0)
 //   3(2) Bogacki-Shampine:  a = (1/2, 3/4), b = (2/9, 1/3, 4/9), a fourth
 //                           stage at the result, bh = (7/24, 1/4, 1/3, 1/8)
-mm_status embedded_step(mm_ctx *c, const float *base, float *out, double h, bool bs23, uint32_t flags, float *err)
+//   5(4) Dormand-Prince:    the published 1980 tableau, seven stages, the
+//                           seventh at the result; rows with several
+//                           nonzero entries read earlier slopes back
+enum class Pair { HeunEuler, BS23, DP54 };
+
+mm_status embedded_step(mm_ctx *c, const float *base, float *out, double h, Pair pair, uint32_t flags, float *err)
 {
     mmk::LocalParams p = local_params(c);
     const bool comp = flags & MM_F_COMPENSATED;
@@ -566,30 +574,52 @@ mm_status embedded_step(mm_ctx *c, const float *base, float *out, double h, bool
     int *flag = c->at<int>(c->o_flag);
     unsigned *emax = reinterpret_cast<unsigned *>(c->at<char>(c->o_flag) + 64);
     const size_t S = 3 * (size_t)c->g.N;
-    float *stage[2] = {c->at<float>(c->o_rk), c->at<float>(c->o_rk) + S};
-    float *acc = c->at<float>(c->o_rk) + 2 * S, *eacc = c->at<float>(c->o_rk) + 3 * S;
-    struct St { float a, b, e; int last, err; };
-    static const St heun[2] = {{1.f, 0.5f, -0.5f, 0, 1}, {0.f, 0.5f, 0.5f, 1, 2}};
-    static const St bs[4] = {{0.5f, 2.f / 9.f, 2.f / 9.f - 7.f / 24.f, 0, 1},
-                             {0.75f, 1.f / 3.f, 1.f / 3.f - 0.25f, 0, 1},
-                             {0.f, 4.f / 9.f, 4.f / 9.f - 1.f / 3.f, 1, 1},
-                             {0.f, 0.f, -0.125f, 2, 2}};
-    const St *tab = bs23 ? bs : heun;
-    const int ns = bs23 ? 4 : 2;
+    float *rk = c->at<float>(c->o_rk);
+    float *stage[2] = {rk, rk + S};
+    float *acc = rk + 2 * S, *eacc = rk + 3 * S, *kbuf = rk + 4 * S;  // kbuf: 4 slopes
+    // a: weight of this stage's k in the next state; ap: weights of the
+    // stored slopes k_0..k_{nprev-1}; last: 0 next state, 1 result, 2 error
+    // only; err: 1 accumulate, 2 accumulate and reduce; kstore: slot or -1
+    struct St {
+        double a, b, e;
+        int last, err, kstore, nprev;
+        double ap[4];
+    };
+    static const St heun[2] = {{1.0, 0.5, -0.5, 0, 1, -1, 0, {0}}, {0.0, 0.5, 0.5, 1, 2, -1, 0, {0}}};
+    static const St bs[4] = {{0.5, 2.0 / 9.0, 2.0 / 9.0 - 7.0 / 24.0, 0, 1, -1, 0, {0}},
+                             {0.75, 1.0 / 3.0, 1.0 / 3.0 - 0.25, 0, 1, -1, 0, {0}},
+                             {0.0, 4.0 / 9.0, 4.0 / 9.0 - 1.0 / 3.0, 1, 1, -1, 0, {0}},
+                             {0.0, 0.0, -0.125, 2, 2, -1, 0, {0}}};
+    static const St dp[7] = {
+        {1.0 / 5.0, 35.0 / 384.0, 35.0 / 384.0 - 5179.0 / 57600.0, 0, 1, 0, 0, {0}},
+        {9.0 / 40.0, 0.0, 0.0, 0, 1, 1, 1, {3.0 / 40.0}},
+        {32.0 / 9.0, 500.0 / 1113.0, 500.0 / 1113.0 - 7571.0 / 16695.0, 0, 1, 2, 2, {44.0 / 45.0, -56.0 / 15.0}},
+        {-212.0 / 729.0, 125.0 / 192.0, 125.0 / 192.0 - 393.0 / 640.0, 0, 1, 3, 3,
+         {19372.0 / 6561.0, -25360.0 / 2187.0, 64448.0 / 6561.0}},
+        {-5103.0 / 18656.0, -2187.0 / 6784.0, -2187.0 / 6784.0 + 92097.0 / 339200.0, 0, 1, -1, 4,
+         {9017.0 / 3168.0, -355.0 / 33.0, 46732.0 / 5247.0, 49.0 / 176.0}},
+        {0.0, 11.0 / 84.0, 11.0 / 84.0 - 187.0 / 2100.0, 1, 1, -1, 0, {0}},
+        {0.0, 0.0, -1.0 / 40.0, 2, 2, -1, 0, {0}}};
+    const St *tab = pair == Pair::HeunEuler ? heun : (pair == Pair::BS23 ? bs : dp);
+    const int ns = pair == Pair::HeunEuler ? 2 : (pair == Pair::BS23 ? 4 : 7);
     MM_TRY(hipcheck(c, hipMemsetAsync(emax, 0, sizeof(unsigned), c->stream), "clear error maximum"));
     const float *eval = base;
     for (int i = 0; i < ns; ++i) {
         float *Hd = nullptr;
         MM_TRY(demag(c, eval, comp, &Hd));
-        p.stage_a = tab[i].a;
-        p.stage_b = tab[i].b;
-        p.stage_e = tab[i].e;
+        const St &t = tab[i];
+        p.stage_a = (float)t.a;
+        p.stage_b = (float)t.b;
+        p.stage_e = (float)t.e;
         p.stage_first = i == 0;
-        p.stage_last = tab[i].last;
-        p.stage_err = tab[i].err;
-        float *o = tab[i].last == 1 ? out : (tab[i].last == 2 ? nullptr : stage[i & 1]);
+        p.stage_last = t.last;
+        p.stage_err = t.err;
+        p.stage_kstore = t.kstore;
+        p.stage_nprev = t.nprev;
+        for (int jj = 0; jj < 6; ++jj) p.stage_ap[jj] = jj < 4 ? (float)t.ap[jj] : 0.f;
+        float *o = t.last == 1 ? out : (t.last == 2 ? nullptr : stage[i & 1]);
         MM_TRY(timed(c, MM_K_LOCAL, "embedded stage", [&] {
-            return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, eacc, (float)h,
+            return mmk::launch_stage(c->g, p, eval, Hd, ms_map_ptr(c), h_map_ptr(c), base, acc, eacc, kbuf, (float)h,
                                      renorm, o, flag, c->stream);
         }));
         if (o) eval = o;
@@ -679,13 +709,16 @@ mm_status mm_step_adaptive(mm_ctx *c, float *m, double t_end, double *dt_io, dou
     if (!(t_end >= 0) || !std::isfinite(t_end)) return fail(c, MM_EINVAL, "t_end must be finite and >= 0");
     if (!(tol > 0) || !std::isfinite(tol)) return fail(c, MM_EINVAL, "tol must be finite and > 0");
     if (max_steps < 1) return fail(c, MM_EINVAL, "max_steps must be >= 1");
-    const bool heun = flags & MM_F_HEUN, bs23 = flags & MM_F_BS23;
-    if (heun == bs23) return fail(c, MM_EINVAL, "exactly one of MM_F_HEUN and MM_F_BS23 selects the pair");
-    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_HEUN | MM_F_BS23))
+    const int heun = (flags & MM_F_HEUN) ? 1 : 0, bs23 = (flags & MM_F_BS23) ? 1 : 0,
+              dp54 = (flags & MM_F_DP54) ? 1 : 0;
+    if (heun + bs23 + dp54 != 1)
+        return fail(c, MM_EINVAL, "exactly one of MM_F_HEUN, MM_F_BS23 and MM_F_DP54 selects the pair");
+    if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_HEUN | MM_F_BS23 | MM_F_DP54))
         return fail(c, MM_EINVAL, "unsupported flag bits 0x%x for adaptive steps", flags);
-    MM_TRY(check_step_args(c, m, 0, *dt_io, flags & ~uint32_t(MM_F_BS23)));
+    MM_TRY(check_step_args(c, m, 0, *dt_io, flags & uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED)));
     MM_TRY(set_device(c));
-    const int q = bs23 ? 2 : 1;  // order of the lower member
+    const Pair pair = heun ? Pair::HeunEuler : (bs23 ? Pair::BS23 : Pair::DP54);
+    const int q = heun ? 1 : (bs23 ? 2 : 4);  // order of the lower member
     float *buf[2] = {m, c->at<float>(c->o_mtmp)};
     int cur = 0;
     double t = 0.0, dt = *dt_io;
@@ -698,7 +731,7 @@ mm_status mm_step_adaptive(mm_ctx *c, float *m, double t_end, double *dt_io, dou
         }
         const double h = (t + dt > t_end) ? t_end - t : dt;
         float err = 0.f;
-        st = embedded_step(c, buf[cur], buf[cur ^ 1], h, bs23, flags, &err);
+        st = embedded_step(c, buf[cur], buf[cur ^ 1], h, pair, flags, &err);
         if (st != MM_OK) break;
         if (!(err == err)) {
             st = fail(c, MM_ENONFINITE, "non-finite error estimate at t = %g s", t);
@@ -1086,6 +1119,8 @@ mmk::LocalParams batch_params(const mm_batch *b)
     const double c1 = -m.gamma0 / (1.0 + m.alpha * m.alpha);
     p.c1 = (float)c1;
     p.c2 = (float)(m.alpha * c1);
+    p.stage_kstore = -1;
+    p.stage_nprev = 0;
     return p;
 }
 

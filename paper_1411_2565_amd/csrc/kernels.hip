@@ -713,7 +713,7 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
         // one explicit Runge-Kutta stage (coefficients in p; the stage
         // states, like the step result, are renormalised unless renorm = 0)
         const bool write_state = p.stage_last != 2;
-        float base[3][V], acc[3][V], er[3][V];
+        float base[3][V], acc[3][V], er[3][V], kv[3][V];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (write_state) {
@@ -734,53 +734,67 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
                 }
             }
         }
-        const float wb = p.stage_b * dt, wa = p.stage_a * dt, we = p.stage_e * dt;
-        float o[3][V], en[V] = {};
-        bool bad = false;
+        // this stage's slope k = f(m, H(m)); zero in vacuum, where the state
+        // stays as it is
 #pragma unroll
         for (int j = 0; j < V; ++j) {
             const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
             const float hx = h[0][j], hy = h[1][j], hz = h[2][j];
             const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
             const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
-            const float kx = p.c1 * ax + p.c2 * bx, ky = p.c1 * ay + p.c2 * by, kz = p.c1 * az + p.c2 * bz;
-            if (!mag[j]) {  // vacuum: k = 0, the state stays as it is
-                en[j] = p.stage_err ? sqrtf(er[0][j] * er[0][j] + er[1][j] * er[1][j] + er[2][j] * er[2][j]) : 0.f;
-                o[0][j] = mx;
-                o[1][j] = my;
-                o[2][j] = mz;
-                continue;
-            }
-            if (p.stage_err) {
-                er[0][j] = fmaf(we, kx, er[0][j]);
-                er[1][j] = fmaf(we, ky, er[1][j]);
-                er[2][j] = fmaf(we, kz, er[2][j]);
+            kv[0][j] = mag[j] ? p.c1 * ax + p.c2 * bx : 0.f;
+            kv[1][j] = mag[j] ? p.c1 * ay + p.c2 * by : 0.f;
+            kv[2][j] = mag[j] ? p.c1 * az + p.c2 * bz : 0.f;
+        }
+        if (p.stage_kstore >= 0) {  // kept for later stages' states
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vstore<V>(D.kbuf + ((long long)p.stage_kstore * 3 + c) * N + i0, kv[c]);
+        }
+        const float wb = p.stage_b * dt, wa = p.stage_a * dt, we = p.stage_e * dt;
+        float o[3][V], en[V] = {};
+        if (p.stage_err) {
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                er[0][j] = fmaf(we, kv[0][j], er[0][j]);
+                er[1][j] = fmaf(we, kv[1][j], er[1][j]);
+                er[2][j] = fmaf(we, kv[2][j], er[2][j]);
                 en[j] = sqrtf(er[0][j] * er[0][j] + er[1][j] * er[1][j] + er[2][j] * er[2][j]);
             }
-            if (!write_state) continue;
-            acc[0][j] = fmaf(wb, kx, acc[0][j]);
-            acc[1][j] = fmaf(wb, ky, acc[1][j]);
-            acc[2][j] = fmaf(wb, kz, acc[2][j]);
-            float nx_, ny_, nz_;
-            if (p.stage_last) {
-                nx_ = acc[0][j];
-                ny_ = acc[1][j];
-                nz_ = acc[2][j];
-            } else {
-                nx_ = fmaf(wa, kx, base[0][j]);
-                ny_ = fmaf(wa, ky, base[1][j]);
-                nz_ = fmaf(wa, kz, base[2][j]);
+        }
+        bool bad = false;
+        if (write_state) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < V; ++j) {
+                    acc[c][j] = fmaf(wb, kv[c][j], acc[c][j]);
+                    o[c][j] = p.stage_last ? acc[c][j] : fmaf(wa, kv[c][j], base[c][j]);
+                }
+            if (!p.stage_last) {
+                // next state: m_base + dt (a k + sum_jj a_jj k_jj), earlier
+                // slopes k_jj read back from the workspace
+                for (int jj = 0; jj < p.stage_nprev; ++jj) {
+                    const float w = p.stage_ap[jj] * dt;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float kp[V];
+                        vload<V>(D.kbuf + ((long long)jj * 3 + c) * N + i0, kp);
+#pragma unroll
+                        for (int j = 0; j < V; ++j) o[c][j] = fmaf(w, kp[j], o[c][j]);
+                    }
+                }
             }
-            if (renorm) {
-                const float sc = rsqrtf(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
-                nx_ *= sc;
-                ny_ *= sc;
-                nz_ *= sc;
+#pragma unroll
+            for (int j = 0; j < V; ++j) {
+                if (!mag[j]) continue;
+                if (renorm) {
+                    const float sc = rsqrtf(o[0][j] * o[0][j] + o[1][j] * o[1][j] + o[2][j] * o[2][j]);
+                    o[0][j] *= sc;
+                    o[1][j] *= sc;
+                    o[2][j] *= sc;
+                }
+                bad |= !(isfinite(o[0][j]) && isfinite(o[1][j]) && isfinite(o[2][j]));
             }
-            bad |= !(isfinite(nx_) && isfinite(ny_) && isfinite(nz_));
-            o[0][j] = nx_;
-            o[1][j] = ny_;
-            o[2][j] = nz_;
         }
         if (p.stage_err == 1) {
 #pragma unroll
@@ -1577,10 +1591,10 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
 }
 
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
-                        const float *h_map, const float *m_base, float *acc, float *eacc, float dt, int renorm,
-                        float *out_m, int *flag, hipStream_t s)
+                        const float *h_map, const float *m_base, float *acc, float *eacc, float *kbuf, float dt,
+                        int renorm, float *out_m, int *flag, hipStream_t s)
 {
-    LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc, eacc};
+    LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc, eacc, kbuf};
     return launch_local_batch(&d, 1, p, 15u, 2, dt, renorm, flag, s);
 }
 

@@ -30,6 +30,10 @@ struct LocalParams {
     //   e' = (first ? 0 : eacc) + stage_e dt k;  1: eacc = e';  2: eacc[0][i] = |e'_i|
     float stage_a, stage_b, stage_e;
     int stage_first, stage_last, stage_err;
+    // full tableau rows: the next state also adds dt sum_{jj < stage_nprev}
+    // stage_ap[jj] kbuf[jj]; stage_kstore >= 0 stores this stage's k there
+    float stage_ap[6];
+    int stage_nprev, stage_kstore;
 };
 
 // Per-sample arguments of one pass.  A launch processes up to kMaxBatch
@@ -67,6 +71,7 @@ struct LocalDesc {
     const float *m_base;  // mode 2: state at the start of the step
     float *acc;           // mode 2: m_base + dt sum_j b_j k_j so far (3N floats)
     float *eacc;          // mode 2: dt sum_j e_j k_j so far (3N floats); per-cell norm at the error stage
+    float *kbuf;          // mode 2: stored slopes k_0, k_1, ... (3N floats each) for tableaus with full rows
 };
 template <typename D, int NB>
 struct Batch {
@@ -121,8 +126,8 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
 // one Runge-Kutta stage (all field terms; coefficients in p.stage_*): reads
 // m (the stage state), Hd = H_demag(m), m_base and acc; writes out_m and acc
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
-                        const float *h_map, const float *m_base, float *acc, float *eacc, float dt, int renorm,
-                        float *out_m, int *flag, hipStream_t s);
+                        const float *h_map, const float *m_base, float *acc, float *eacc, float *kbuf, float dt,
+                        int renorm, float *out_m, int *flag, hipStream_t s);
 // out (one unsigned, zeroed by the caller) <- bits of max(e[0..n)) for e >= 0
 // or NaN (NaN wins: its bit pattern orders above every finite value)
 hipError_t launch_errmax(const float *e, long long n, unsigned *out, hipStream_t s);

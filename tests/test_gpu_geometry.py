@@ -67,7 +67,7 @@ def test_disk_heff_energy_and_trajectory(gpu_lib):
     sim.close()
 
 
-@pytest.mark.parametrize("mode", ["rk4", "adaptive"])
+@pytest.mark.parametrize("mode", ["rk4", "adaptive", "adaptive_dp54"])
 def test_disk_runge_kutta(gpu_lib, mode):
     w, sim, P, m, mag = disk_case(gpu_lib)
     mf = host(m)
@@ -75,8 +75,9 @@ def test_disk_runge_kutta(gpu_lib, mode):
         sim.step(m, 40, w.dt, gpu_lib.MM_F_RK4)
         mo = P.run(mf, 40, w.dt, method="rk4")
     else:
-        dt, acc, rej = sim.run_adaptive(m, 2e-12, w.dt, 1e-5, gpu_lib.MM_F_BS23)
-        mo, dto, acco, rejo = P.run_adaptive(mf, 2e-12, w.dt, 1e-5, "bs23")
+        dp = mode == "adaptive_dp54"
+        dt, acc, rej = sim.run_adaptive(m, 2e-12, w.dt, 1e-5, gpu_lib.MM_F_DP54 if dp else gpu_lib.MM_F_BS23)
+        mo, dto, acco, rejo = P.run_adaptive(mf, 2e-12, w.dt, 1e-5, "dp54" if dp else "bs23")
         print(f"adaptive: GPU {acc}/{rej}, oracle {acco}/{rejo}")
         assert abs(acc - acco) <= max(2, 0.05 * acco)
     sim.sync()

@@ -136,7 +136,7 @@ def test_rk4_energy_non_increasing_at_film_dt(gpu_lib):
     assert E[-1] < E[0]
 
 
-@pytest.mark.parametrize("pair", ["heun_euler", "bs23"])
+@pytest.mark.parametrize("pair", ["heun_euler", "bs23", "dp54"])
 def test_adaptive_matches_oracle(gpu_lib, pair):
     """Adaptive steps (Sec. 6's future-work item) on the 16x16x2 block with
     anisotropy and a field, to t = 1e-11 s at tol = 1e-5: the GPU's FP32
@@ -146,7 +146,7 @@ def test_adaptive_matches_oracle(gpu_lib, pair):
     m0, _ = workloads.inputs(w)
     h = (2e4, -1e4, 5e3)
     kw = dict(Ms=w.Ms, A=w.A, Ku=3e4, u=(0.0, 0.6, 0.8), alpha=w.alpha)
-    fl = gpu_lib.MM_F_HEUN if pair == "heun_euler" else gpu_lib.MM_F_BS23
+    fl = {"heun_euler": gpu_lib.MM_F_HEUN, "bs23": gpu_lib.MM_F_BS23, "dp54": gpu_lib.MM_F_DP54}[pair]
     sim = gpu_lib.Sim(w.n, w.d, hext=h, **kw)
     m = gpu(m0)
     mf = host(m)
@@ -169,7 +169,7 @@ def test_adaptive_argument_errors(gpu_lib):
     m = gpu(workloads.inputs(w)[0])
     dt, acc, rej = sim.run_adaptive(m, 0.0, 1e-13, 1e-5, b.MM_F_HEUN)
     assert (acc, rej) == (0, 0)
-    for flags in (0, b.MM_F_HEUN | b.MM_F_BS23, b.MM_F_RK4, b.MM_F_HEUN | b.MM_F_GRAPH):
+    for flags in (0, b.MM_F_HEUN | b.MM_F_BS23, b.MM_F_BS23 | b.MM_F_DP54, b.MM_F_RK4, b.MM_F_HEUN | b.MM_F_GRAPH):
         with pytest.raises(b.MMError) as ei:
             sim.run_adaptive(m, 1e-12, 1e-13, 1e-5, flags)
         assert ei.value.code == b.MM_EINVAL
