@@ -114,38 +114,71 @@ __host__ __device__ constexpr int elems_per_thread(int L) { return L < 8 ? L : 8
 // points remain: as large as the per-thread element count allows
 __host__ __device__ constexpr int stage_radix(int rem, int E) { return rem < E ? rem : E; }
 
-// Stages of an FFT of length L over NC lines held by one thread group:
-// v[c][q] = line c, position t + q*(L/E).  lds[c] is line c's exchange buffer
-// (lds_line(L) complex).  Every thread of the block must take part: the
-// exchange uses block barriers.
-template <int L, int E, int NC, int Ns, bool INV>
-__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t);
-
-template <int L, int E, int NC, int Ns, bool INV>
-__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *(&lds)[NC], int t)
+// Twiddles one thread needs over all stages of a length-L FFT with E points
+// per thread: w and w^2 (w alone for radix 2) of each of its butterflies in
+// every stage after the first.  Loaded together, while the data loads are in
+// flight, they keep table-load latency off the chain of barriers between
+// stages (the loads had been issued after each barrier); one set serves the
+// forward and the inverse transform (conjugated).
+__host__ __device__ constexpr int tw_offset(int L, int E, int Ns_end)
 {
-    fft_stages<L, E, NC, Ns, INV>(v, const_cast<float2 *const (&)[NC]>(lds), t);
+    int n = 0;
+    for (int Ns = 1; Ns < L && Ns < Ns_end;) {
+        const int R = stage_radix(L / Ns, E);
+        if (Ns > 1) n += (E / R) * (R > 2 ? 2 : 1);
+        Ns *= R;
+    }
+    return n;
 }
 
+template <int L, int E>
+struct TwSet {
+    static constexpr int N = tw_offset(L, E, L);
+    float2 w[N > 0 ? N : 1];
+};
+
+template <int L, int E, int Ns = 1>
+__device__ __forceinline__ void load_twiddles(TwSet<L, E> &s, int t)
+{
+    if constexpr (Ns < L) {
+        constexpr int R = stage_radix(L / Ns, E), NB = E / R, T = L / E, G = R > 2 ? 2 : 1;
+        constexpr int off = tw_offset(L, E, Ns);
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int k = (t + i * T) & (Ns - 1);
+                s.w[off + i * G] = twiddle<false>(k, Ns * R);
+                if constexpr (R > 2) s.w[off + i * G + 1] = twiddle<false>(2 * k, Ns * R);
+            }
+        }
+        load_twiddles<L, E, Ns * R>(s, t);
+    }
+}
+
+// Stages of an FFT of length L over NC lines held by one thread group:
+// v[c][q] = line c, position t + q*(L/E).  lds[c] is line c's exchange buffer
+// (lds_line(L) complex); tw holds this thread's twiddles (load_twiddles).
+// Every thread of the block must take part: the exchange uses block barriers.
 template <int L, int E, int NC, int Ns, bool INV>
-__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
+__device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t,
+                                           const TwSet<L, E> &tw)
 {
     if constexpr (Ns < L) {
         constexpr int R = stage_radix(L / Ns, E);
         constexpr int NB = E / R;      // butterflies per thread in this stage
         constexpr int T = L / E;       // threads per line
         constexpr bool last = (Ns * R == L);
+        constexpr int off = tw_offset(L, E, Ns), G = R > 2 ? 2 : 1;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int j = t + i * T;
             const int k = j & (Ns - 1);
+            // w^r from w, w^2 and at most three complex products
             float2 w[R];
             if constexpr (Ns > 1) {
-                // w^r from two table loads (w, w^2) and at most three complex
-                // products: table loads, not arithmetic, bound these passes
-                w[1] = twiddle<INV>(k, Ns * R);
+                w[1] = INV ? cconj(tw.w[off + i * G]) : tw.w[off + i * G];
                 if constexpr (R > 2) {
-                    w[2] = twiddle<INV>(2 * k, Ns * R);
+                    w[2] = INV ? cconj(tw.w[off + i * G + 1]) : tw.w[off + i * G + 1];
 #pragma unroll
                     for (int r = 3; r < R; ++r) w[r] = cmul(w[r - 2], w[2]);
                 }
@@ -177,18 +210,29 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&l
 #pragma unroll
                 for (int q = 0; q < E; ++q) v[c][q] = lds[c][lpad(t + q * T)];
             __syncthreads();
-            fft_stages<L, E, NC, Ns * R, INV>(v, lds, t);
+            fft_stages<L, E, NC, Ns * R, INV>(v, lds, t, tw);
         }
     }
 }
 
-// In-register FFT of NC lines per thread group (see fft_stages).  On entry
-// and exit v[c][q] holds position t + q*(L/E) of line c, natural order.
+// In-register FFT of NC lines per thread group (see fft_stages) with
+// twiddles from a set filled by load_twiddles<L, E>.  On entry and exit
+// v[c][q] holds position t + q*(L/E) of line c, natural order.
+template <int L, bool INV, int NC, int E>
+__device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t, const TwSet<L, E> &tw)
+{
+    static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
+    fft_stages<L, E, NC, 1, INV>(v, lds, t, tw);
+}
+
+// The same, loading the twiddle set on entry (issued before the first stage
+// waits for the data in v).
 template <int L, bool INV, int NC, int E>
 __device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
 {
-    static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
-    fft_stages<L, E, NC, 1, INV>(v, lds, t);
+    TwSet<L, E> tw;
+    load_twiddles<L, E>(tw, t);
+    reg_fft<L, INV>(v, lds, t, tw);
 }
 
 }  // namespace mmk

@@ -400,15 +400,18 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, 
             v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[c * cs + zz * zs]
                                                            : make_float2(0.f, 0.f);
         }
-    float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
-                            sm + (2 * CB + col) * lds_line(L)};
-    reg_fft<L, false>(v, lds, t);
+    // one twiddle set for both transforms, loaded while the data arrive
+    TwSet<L, E> tw;
+    load_twiddles<L, E>(tw, t);
     const int hy = g.Py / 2, hz = g.Pz / 2;
     const bool fy = ky > hy;
     const int kyf = fy ? g.Py - ky : ky;
     const float sy = fy ? -1.f : 1.f;
     // this column's octant entries: K[kx][kyf][kz][6], contiguous over kz
     const float *kcol = K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
+    float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
+                            sm + (2 * CB + col) * lds_line(L)};
+    reg_fft<L, false>(v, lds, t, tw);
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int kz = t + q * T;
@@ -435,7 +438,7 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, 
             v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
         }
     }
-    reg_fft<L, true>(v, lds, t);
+    reg_fft<L, true>(v, lds, t, tw);
     if (ok) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
