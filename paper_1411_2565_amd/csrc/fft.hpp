@@ -222,17 +222,26 @@ template <int L, bool INV, int NC, int E>
 __device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t, const TwSet<L, E> &tw)
 {
     static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
+    // Wait for the whole set here, before the first stage.  Left to itself
+    // the compiler waits for the last stage's twiddles only when it needs
+    // them, which can fall after the caller's first output stores; one
+    // counter tracks vector-memory loads and stores alike, so that wait would
+    // also hold until those stores complete.
+#pragma unroll
+    for (int i = 0; i < TwSet<L, E>::N; ++i) asm volatile("" ::"v"(tw.w[i].x), "v"(tw.w[i].y));
     fft_stages<L, E, NC, 1, INV>(v, lds, t, tw);
 }
 
 // The same, loading the twiddle set on entry (issued before the first stage
-// waits for the data in v).
+// waits for the data in v); for callers whose stores all follow the last
+// stage, so no early wait is needed.
 template <int L, bool INV, int NC, int E>
 __device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
 {
+    static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
     TwSet<L, E> tw;
     load_twiddles<L, E>(tw, t);
-    reg_fft<L, INV>(v, lds, t, tw);
+    fft_stages<L, E, NC, 1, INV>(v, lds, t, tw);
 }
 
 }  // namespace mmk

@@ -183,34 +183,56 @@ __global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xfwd(Batch<XfwdDesc
     const bool ok = y < g.ny;
     const long long cell0 = ((long long)z * g.ny + y) * g.nx;
     const float *row = m + (long long)c * g.N + cell0;
-    float2 v[1][E];
-    const bool even = (g.nx & 1) == 0;
+    // every load of the tile is issued before any arithmetic on it
+    float2 a[E], sc[E];
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-        const int k = t + q * T, x0 = 2 * k;
-        float2 a = make_float2(0.f, 0.f);
-        if (q < half_elems(E) && ok && x0 < g.nx) {
-            if (even) {
-                a = *reinterpret_cast<const float2 *>(row + x0);
-                if (ms_map) {
-                    const float2 s = *reinterpret_cast<const float2 *>(ms_map + cell0 + x0);
-                    a.x *= s.x;
-                    a.y *= s.y;
-                } else {
-                    a.x *= ms;
-                    a.y *= ms;
-                }
-            } else {
-                a.x = row[x0] * (ms_map ? ms_map[cell0 + x0] : ms);
-                if (x0 + 1 < g.nx) a.y = row[x0 + 1] * (ms_map ? ms_map[cell0 + x0 + 1] : ms);
+        a[q] = make_float2(0.f, 0.f);
+        sc[q] = make_float2(ms, ms);
+    }
+    if ((g.nx & 1) == 0) {
+        // loads from clamped addresses need no branch; lanes past the row's
+        // end or the last row take their zero afterwards
+        const long long cellc = ((long long)z * g.ny + (ok ? y : g.ny - 1)) * g.nx;
+        const float *rowc = m + (long long)c * g.N + cellc;
+#pragma unroll
+        for (int q = 0; q < half_elems(E); ++q) {
+            const int x0 = 2 * (t + q * T);
+            const float2 val = *reinterpret_cast<const float2 *>(rowc + min(x0, g.nx - 2));
+            a[q] = (ok && x0 < g.nx) ? val : make_float2(0.f, 0.f);
+        }
+        if (ms_map) {
+#pragma unroll
+            for (int q = 0; q < half_elems(E); ++q) {
+                const int x0 = 2 * (t + q * T);
+                const float2 val = *reinterpret_cast<const float2 *>(ms_map + cellc + min(x0, g.nx - 2));
+                sc[q] = (ok && x0 < g.nx) ? val : sc[q];
             }
         }
-        v[0][q] = a;
+    } else {
+#pragma unroll
+        for (int q = 0; q < half_elems(E); ++q) {
+            const int x0 = 2 * (t + q * T);
+            if (ok && x0 < g.nx) {
+                a[q].x = row[x0];
+                if (ms_map) sc[q].x = ms_map[cell0 + x0];
+                if (x0 + 1 < g.nx) {
+                    a[q].y = row[x0 + 1];
+                    if (ms_map) sc[q].y = ms_map[cell0 + x0 + 1];
+                }
+            }
+        }
     }
+    TwSet<L, E> twl;
+    load_twiddles<L, E>(twl, t);
+    float2 v[1][E];
+#pragma unroll
+    for (int q = 0; q < E; ++q)  // the upper half stays a compile-time zero
+        v[0][q] = q < half_elems(E) ? make_float2(a[q].x * sc[q].x, a[q].y * sc[q].y) : make_float2(0.f, 0.f);
     float2 *const tw = sm + LPB * LD;
     load_half_twiddles<L, S::THREADS>(tw);
     float2 *const lds[1] = {sm + ll * LD};
-    reg_fft<L, false>(v, lds, t);
+    reg_fft<L, false>(v, lds, t, twl);
 #pragma unroll
     for (int q = 0; q < E; ++q) sm[ll * LD + t + q * T] = v[0][q];
     __syncthreads();
@@ -484,6 +506,9 @@ __global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(Batch<XinvDesc
         const int kx = idx / LPB, yl = idx - kx * LPB;
         tile[it] = (idx < (L + 1) * LPB && yl < nl) ? in[(long long)kx * g.ny + yl] : make_float2(0.f, 0.f);
     }
+    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
+    TwSet<L, E> twl;
+    load_twiddles<L, E>(twl, t);
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int idx = threadIdx.x + it * S::THREADS;
@@ -491,7 +516,6 @@ __global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(Batch<XinvDesc
         if (idx < (L + 1) * LPB) sm[yl * LD + kx] = tile[it];
     }
     __syncthreads();
-    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
     float2 v[1][E];
     {
         const float2 *X = sm + ll * LD;
@@ -506,7 +530,7 @@ __global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(Batch<XinvDesc
     }
     __syncthreads();
     float2 *const lds[1] = {sm + ll * LD};
-    reg_fft<L, true>(v, lds, t);
+    reg_fft<L, true>(v, lds, t, twl);
     if (ll < nl) {
         float *out = Hd + (long long)c * g.N + ((long long)z * g.ny + y0 + ll) * g.nx;
         const bool even = (g.nx & 1) == 0;
@@ -564,6 +588,21 @@ __device__ __forceinline__ void vstore(float *p, const float (&o)[V])
     }
 }
 
+#ifndef MMK_LOCAL_XCD
+#define MMK_LOCAL_XCD 1
+#endif
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Within every run of 64 blocks, XCD x takes the 8 consecutive blocks
+// 8x .. 8x+7: a block's y-neighbour rows then sit mostly in blocks of the
+// same XCD, and when a z-plane spans a multiple of 64 blocks its z-neighbour
+// rows do too (64 blocks apart).  A bijection on [0, nb) for nb % 64 == 0.
+__device__ __forceinline__ int local_block(int b, int nb)
+{
+    if (!MMK_LOCAL_XCD || (nb & 63) != 0) return b;
+    const int x = b & 7, k = b >> 3;
+    return ((k >> 3) << 6) | (x << 3) | (k & 7);
+}
+
 // MAPPED: the samples carry an Ms map (per-cell Ms, and vacuum where it is 0);
 // without one the kernel compiles to the uniform-Ms code alone.
 template <int MODE, int V, int NB, bool MAPPED>
@@ -578,7 +617,7 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     const float *__restrict__ h_map = D.h_map;
     float *__restrict__ out_m = D.m_out;
     float *__restrict__ out_h = D.h_out;
-    const long long i0 = ((long long)blockIdx.x * kThreads + threadIdx.x) * V;
+    const long long i0 = ((long long)local_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x) * V;
     if (i0 >= g.N) return;
     const long long N = g.N;
     const int x0 = (int)(i0 % g.nx);
@@ -621,16 +660,21 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int j = 0; j < V; ++j) lap[c][j] = 0.f;
-        // x neighbours: inside the vector, plus one scalar on each side
-        bool has_l = x0 > 0, has_r = x0 + V < g.nx;
+        // x neighbours: inside the vector, plus one scalar on each side.  All
+        // neighbour loads are unconditional, so they issue together: where
+        // there is no neighbour (the sample's free surface) the cell itself is
+        // read, and its term is not added (x) or adds exactly zero (y, z).
+        const bool gl = x0 > 0, gr = x0 + V < g.nx;
+        const long long il = gl ? i0 - 1 : i0, ir = gr ? i0 + V : i0 + V - 1;
+        bool has_l = gl, has_r = gr;
         if constexpr (MAPPED) {
-            has_l = has_l && ms_map[i0 - 1] > 0.f;
-            has_r = has_r && ms_map[i0 + V] > 0.f;
+            has_l = has_l && ms_map[il] > 0.f;
+            has_r = has_r && ms_map[ir] > 0.f;
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float left = has_l ? m[c * N + i0 - 1] : 0.f;
-            const float right = has_r ? m[c * N + i0 + V] : 0.f;
+            const float left = m[c * N + il];
+            const float right = m[c * N + ir];
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const float a = mc[c][j];
@@ -669,10 +713,10 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
                     if (nbm[j]) lap[c][j] = fmaf(w, nb[j] - mc[c][j], lap[c][j]);
             }
         };
-        if (y > 0) add(-sy, p.ay);
-        if (y < g.ny - 1) add(sy, p.ay);
-        if (z > 0) add(-sz, p.az);
-        if (z < g.nz - 1) add(sz, p.az);
+        add(y > 0 ? -sy : 0, p.ay);
+        add(y < g.ny - 1 ? sy : 0, p.ay);
+        add(z > 0 ? -sz : 0, p.az);
+        add(z < g.nz - 1 ? sz : 0, p.az);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
