@@ -588,19 +588,28 @@ __device__ __forceinline__ void vstore(float *p, const float (&o)[V])
     }
 }
 
-#ifndef MMK_LOCAL_XCD
-#define MMK_LOCAL_XCD 1
-#endif
 // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Within every run of 64 blocks, XCD x takes the 8 consecutive blocks
-// 8x .. 8x+7: a block's y-neighbour rows then sit mostly in blocks of the
-// same XCD, and when a z-plane spans a multiple of 64 blocks its z-neighbour
-// rows do too (64 blocks apart).  A bijection on [0, nb) for nb % 64 == 0.
-__device__ __forceinline__ int local_block(int b, int nb)
+// When a z-plane spans P = 8q blocks and the launch covers whole planes, XCD
+// x takes blocks x*q .. x*q + q - 1 of every plane (q from the launcher):
+// a block's z-neighbour rows (P blocks away) are then always, and its
+// y-neighbour rows (the adjacent blocks) mostly, read through the same L2.
+// q = 0 keeps the launch order.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int local_block(int b, int q)
 {
-    if (!MMK_LOCAL_XCD || (nb & 63) != 0) return b;
-    const int x = b & 7, k = b >> 3;
-    return ((k >> 3) << 6) | (x << 3) | (k & 7);
+    if (q <= 0) return b;
+    const int k = b >> 3;
+    return (k / q) * (8 * q) + (b & 7) * q + k % q;
+}
+
+// q for local_block: the z-plane of g spans P = 8q blocks of `cells` cells,
+// and the nb blocks of the launch cover whole planes; else 0
+static int local_perm_q(const Geo &g, long long cells, long long nb)
+{
+    const long long plane = (long long)g.nx * g.ny;
+    if (plane % cells != 0) return 0;
+    const long long P = plane / cells;
+    if (P % 8 != 0 || nb % P != 0) return 0;
+    return (int)(P / 8);
 }
 
 // MAPPED: the samples carry an Ms map (per-cell Ms, and vacuum where it is 0);
@@ -617,7 +626,7 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     const float *__restrict__ h_map = D.h_map;
     float *__restrict__ out_m = D.m_out;
     float *__restrict__ out_h = D.h_out;
-    const long long i0 = ((long long)local_block(blockIdx.x, gridDim.x) * kThreads + threadIdx.x) * V;
+    const long long i0 = ((long long)local_block(blockIdx.x, D.perm_q) * kThreads + threadIdx.x) * V;
     if (i0 >= g.N) return;
     const long long N = g.N;
     const int x0 = (int)(i0 % g.nx);
@@ -1572,6 +1581,12 @@ hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &
     dim3 grid((unsigned)((items + kThreads - 1) / kThreads), 1, count);
     bool mapped = false;
     for (int i = 0; i < count; ++i) mapped = mapped || d[i].ms_map != nullptr;
+    LocalDesc dq[kMaxBatch];
+    for (int i = 0; i < count; ++i) {
+        dq[i] = d[i];
+        dq[i].perm_q = local_perm_q(d[i].g, (long long)kThreads * (vec ? 4 : 1), grid.x);
+    }
+    d = dq;
 #define LOCAL(MODE, V)                                                                        \
     do {                                                                                      \
         if (count == 1) {                                                                     \

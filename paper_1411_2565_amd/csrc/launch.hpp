@@ -72,6 +72,7 @@ struct LocalDesc {
     float *acc;           // mode 2: m_base + dt sum_j b_j k_j so far (3N floats)
     float *eacc;          // mode 2: dt sum_j e_j k_j so far (3N floats); per-cell norm at the error stage
     float *kbuf;          // mode 2: stored slopes k_0, k_1, ... (3N floats each) for tableaus with full rows
+    int perm_q;           // set by the launcher: blocks per XCD per z-plane of the block order (0: launch order)
 };
 template <typename D, int NB>
 struct Batch {
