@@ -155,11 +155,28 @@ __device__ __forceinline__ void load_twiddles(TwSet<L, E> &s, int t)
     }
 }
 
+// Orders one stage's LDS writes before the next stage's reads, and those
+// reads before the writes after them.  WAVE: every line lies within one
+// wavefront, whose LDS operations execute in issue order, so only the
+// compiler has to be kept from moving them (a fence at wavefront scope);
+// otherwise a block barrier.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Stages of an FFT of length L over NC lines held by one thread group:
 // v[c][q] = line c, position t + q*(L/E).  lds[c] is line c's exchange buffer
 // (lds_line(L) complex); tw holds this thread's twiddles (load_twiddles).
 // Every thread of the block must take part: the exchange uses block barriers.
-template <int L, int E, int NC, int Ns, bool INV>
+template <int L, int E, int NC, int Ns, bool INV, bool WAVE>
 __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t,
                                            const TwSet<L, E> &tw)
 {
@@ -204,23 +221,27 @@ __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&l
             }
         }
         if constexpr (!last) {
-            __syncthreads();
+            exchange_sync<WAVE>();
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
                 for (int q = 0; q < E; ++q) v[c][q] = lds[c][lpad(t + q * T)];
-            __syncthreads();
-            fft_stages<L, E, NC, Ns * R, INV>(v, lds, t, tw);
+            exchange_sync<WAVE>();
+            fft_stages<L, E, NC, Ns * R, INV, WAVE>(v, lds, t, tw);
         }
     }
 }
 
 // In-register FFT of NC lines per thread group (see fft_stages) with
 // twiddles from a set filled by load_twiddles<L, E>.  On entry and exit
-// v[c][q] holds position t + q*(L/E) of line c, natural order.
-template <int L, bool INV, int NC, int E>
+// v[c][q] holds position t + q*(L/E) of line c, natural order.  WAVE: the
+// caller lays each line's L/E threads out as consecutive lanes of one
+// wavefront (thread = line * (L/E) + t, L/E <= 64), so the stages need no
+// block barrier.
+template <int L, bool INV, bool WAVE = false, int NC, int E>
 __device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t, const TwSet<L, E> &tw)
 {
+    static_assert(!WAVE || (L / E <= 64 && (64 % (L / E)) == 0), "a line must lie within one wavefront");
     static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
     // Wait for the whole set here, before the first stage.  Left to itself
     // the compiler waits for the last stage's twiddles only when it needs
@@ -229,19 +250,20 @@ __device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)
     // also hold until those stores complete.
 #pragma unroll
     for (int i = 0; i < TwSet<L, E>::N; ++i) asm volatile("" ::"v"(tw.w[i].x), "v"(tw.w[i].y));
-    fft_stages<L, E, NC, 1, INV>(v, lds, t, tw);
+    fft_stages<L, E, NC, 1, INV, WAVE>(v, lds, t, tw);
 }
 
 // The same, loading the twiddle set on entry (issued before the first stage
 // waits for the data in v); for callers whose stores all follow the last
 // stage, so no early wait is needed.
-template <int L, bool INV, int NC, int E>
+template <int L, bool INV, bool WAVE = false, int NC, int E>
 __device__ __forceinline__ void reg_fft(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t)
 {
     static_assert(E >= 1 && E <= L && (L % E) == 0, "element count");
+    static_assert(!WAVE || (L / E <= 64 && (64 % (L / E)) == 0), "a line must lie within one wavefront");
     TwSet<L, E> tw;
     load_twiddles<L, E>(tw, t);
-    fft_stages<L, E, NC, 1, INV>(v, lds, t, tw);
+    fft_stages<L, E, NC, 1, INV, WAVE>(v, lds, t, tw);
 }
 
 }  // namespace mmk
