@@ -117,9 +117,8 @@ __host__ __device__ constexpr int stage_radix(int rem, int E) { return rem < E ?
 // Twiddles one thread needs over all stages of a length-L FFT with E points
 // per thread: w and w^2 (w alone for radix 2) of each of its butterflies in
 // every stage after the first.  Loaded together, while the data loads are in
-// flight, they keep table-load latency off the chain of barriers between
-// stages (the loads had been issued after each barrier); one set serves the
-// forward and the inverse transform (conjugated).
+// flight, they keep table-load latency off the chain of exchanges between
+// stages; one set serves the forward and the inverse transform (conjugated).
 __host__ __device__ constexpr int tw_offset(int L, int E, int Ns_end)
 {
     int n = 0;
