@@ -168,6 +168,26 @@ def test_trajectory_split_calls_equal_one_call(gpu_lib):
     assert torch.equal(c, gpu(m0))
 
 
+def test_block_steps_are_deterministic(gpu_lib):
+    """The 256x256x32 block, 50 steps from the same state twice: equal bit
+    for bit.  The x passes and the y-inverse order their FFT exchanges
+    within each wavefront instead of by block barriers; a missing ordering
+    would show up as run-to-run differences here, at the full grid."""
+    import torch
+    w = workloads.BLOCK_256x256x32
+    m0, _ = workloads.inputs(w)
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    a, b = gpu(m0), gpu(m0)
+    sim.step(a, 50, w.dt)
+    sim.step(b, 50, w.dt)
+    h1 = sim.heff(a)
+    h2 = sim.heff(a)
+    sim.sync()
+    assert torch.equal(a, b)
+    assert torch.equal(h1, h2)
+    sim.close()
+
+
 def test_norm_identity_without_renorm(gpu_lib):
     w, m0, args = _block16()
     sim = gpu_lib.Sim(w.n, w.d, **args)
