@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MEASURED_TRAFFIC = {
     # k_zconv<64, false, 0, 1>: FETCH_SIZE 76 681.0 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
     "zconv": {"bytes_per_launch": 258099200,
-              "source_sha": "d08ec0095d26ca3ba56916cd815139a5f8a75eb1b1ca4a1edfe307ab7a43fd65"},
+              "source_sha": "30d10af85ce08350c1e218159e3d1a4ba75a076616a36212abdbac25c9929d6a"},
 }
 
 def kernel_source_sha():

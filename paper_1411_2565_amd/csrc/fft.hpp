@@ -174,7 +174,8 @@ __device__ __forceinline__ void exchange_sync()
 // Stages of an FFT of length L over NC lines held by one thread group:
 // v[c][q] = line c, position t + q*(L/E).  lds[c] is line c's exchange buffer
 // (lds_line(L) complex); tw holds this thread's twiddles (load_twiddles).
-// Every thread of the block must take part: the exchange uses block barriers.
+// Every thread of the block (WAVE: of the line's wavefront) must take part,
+// as the exchanges are ordered by block barriers (WAVE: wavefront fences).
 template <int L, int E, int NC, int Ns, bool INV, bool WAVE>
 __device__ __forceinline__ void fft_stages(float2 (&v)[NC][E], float2 *const (&lds)[NC], int t,
                                            const TwSet<L, E> &tw)
