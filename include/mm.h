@@ -282,7 +282,7 @@ mm_status mm_kernel_times(mm_ctx *c, double *ms, int64_t *launches);
  * Many independent grids of rectangular cells (one cell size and material,
  * each its own nx, ny, nz and uniform external field) advanced together by
  * the same step as mm_step_llg.  Samples with equal padded sizes share one
- * tensor spectrum and one launch per pass (up to 32 samples per launch).
+ * tensor spectrum and one launch per pass (up to 64 samples per launch).
  * The state of all samples is one packed FP32 device array: sample b's
  * [3][nz][ny][nx] block starts at float offset offsets[b]
  * (mm_batch_state_offsets), each block 16-byte aligned. */

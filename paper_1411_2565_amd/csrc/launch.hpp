@@ -39,7 +39,7 @@ struct LocalParams {
 // Per-sample arguments of one pass.  A launch processes up to kMaxBatch
 // samples of one padded size; the descriptors travel by value in the kernel
 // arguments and blockIdx.z selects the sample.
-constexpr int kMaxBatch = 32;
+constexpr int kMaxBatch = 64;
 struct XfwdDesc {
     Geo g;
     const float *m;       // state [3][nz][ny][nx]
