@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MEASURED_TRAFFIC = {
     # k_zconv<64, false, 0, 1>: FETCH_SIZE 76 681.9 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
     "zconv": {"bytes_per_launch": 258101043,
-              "source_sha": "f4db2c68f9d84882859dc76158842a7ceb86240a96bf7c0a919de5042f1369e1"},
+              "source_sha": "2ecf34e2d411beb76c3ee68863004bad7875f3bcd9bb866665c01446b0c08849"},
 }
 
 def kernel_source_sha():

@@ -78,6 +78,12 @@ template <typename D, int NB>
 struct Batch {
     D s[NB];
 };
+// Batched descriptors travel by value in the kernel arguments; by-value
+// arguments of up to 20.8 KB were checked to arrive intact on gfx950.
+static_assert(sizeof(Batch<LocalDesc, kMaxBatch>) + sizeof(LocalParams) + 64 <= 20800, "batch arguments too large");
+static_assert(sizeof(Batch<XfwdDesc, kMaxBatch>) <= 20800 && sizeof(Batch<XinvDesc, kMaxBatch>) <= 20800 &&
+                  sizeof(Batch<YDesc, kMaxBatch>) <= 20800 && sizeof(Batch<ZDesc, kMaxBatch>) <= 20800,
+              "batch arguments too large");
 
 // FP64 energy coefficients.
 struct EnergyParams {
