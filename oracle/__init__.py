@@ -72,6 +72,12 @@ def lib():
         L.orc_adjoint.restype = ctypes.c_double
         L.orc_step_cells.argtypes = [P, _D, _I64, ctypes.c_int64, ctypes.c_double, _D]
         L.orc_threads.restype = ctypes.c_int
+        L.orc_field_scale.argtypes = [ctypes.c_double] * 4
+        L.orc_field_scale.restype = ctypes.c_double
+        L.orc_run_scheduled.argtypes = [P, _D, ctypes.c_int64] + [ctypes.c_double] * 5
+        L.orc_run_scheduled.restype = ctypes.c_double
+        L.orc_loss.argtypes = [_D, _D, ctypes.c_int64]
+        L.orc_loss.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -206,6 +212,16 @@ class Problem:
                       _p(tr) if traj else ctypes.cast(None, _D))
         return (m, tr) if traj else m
 
+    def run_scheduled(self, m0, nsteps, dt, schedule, t0=0.0):
+        """nsteps Euler steps with the external field switched by ``schedule``
+        = (t_start, t_decay, t_stop) in seconds (off, full, linear decay, off;
+        see ``field_scale``), the first step at time t0.  Returns (m, t_end)."""
+        m = _f64(m0, self._shape()).copy()
+        st = self._struct()
+        ts, td, tp = (float(v) for v in schedule)
+        t = lib().orc_run_scheduled(ctypes.byref(st), _p(m), int(nsteps), float(dt), float(t0), ts, td, tp)
+        return m, t
+
     PAIRS = {"heun_euler": 1, "bs23": 2, "dp54": 3}
 
     def run_adaptive(self, m0, t_end, dt0, tol, pair="heun_euler", max_steps=10**6):
@@ -253,6 +269,22 @@ class Problem:
         loss = lib().orc_adjoint(ctypes.byref(st), _p(m0), int(nsteps), float(dt), _p(t),
                                  _p(gm), _p(gh), _p(gms))
         return loss, gm, gh, gms
+
+
+def field_scale(t, schedule):
+    """Profile of the time-dependent external field at time t for
+    schedule = (t_start, t_decay, t_stop): 0 before t_start, 1 up to
+    t_decay, linear to 0 at t_stop, 0 after."""
+    return lib().orc_field_scale(float(t), *(float(v) for v in schedule))
+
+
+def loss(m, t):
+    """1/2 sum (m - t)^2 over all components, FP64."""
+    m = _f64(m).ravel()
+    t = _f64(t).ravel()
+    if m.size != t.size:
+        raise ValueError("m and t differ in size")
+    return lib().orc_loss(_p(m), _p(t), m.size)
 
 
 def threads():

@@ -584,6 +584,57 @@ void orc_run(const orc_problem *p, double *m, int64_t nsteps, double dt, double 
 }
 
 /* ------------------------------------------------------------------------ */
+/* Time-dependent external field.  The paper's input file (Sec. 5) gives the  */
+/* field as Hx Hy Hz with a startTime, a decayTime and a stopTime and does    */
+/* not define the profile between them.  Read here as: off before startTime, */
+/* full strength from startTime to decayTime, a linear decay to zero between */
+/* decayTime and stopTime, off from stopTime on.  The profile multiplies the */
+/* whole external field (uniform or per cell).  Times are absolute, in       */
+/* seconds; step n of an Euler run evaluates its field at t_n, with          */
+/* t_{n+1} = t_n + dt accumulated in FP64.                                   */
+/* ------------------------------------------------------------------------ */
+double orc_field_scale(double t, double t_start, double t_decay, double t_stop)
+{
+    if (t < t_start) return 0.0;
+    if (t <= t_decay) return 1.0;
+    if (t >= t_stop) return 0.0;
+    return (t_stop - t) / (t_stop - t_decay);
+}
+
+/* nsteps Euler steps from m (in place) with the external field of p scaled
+ * by the profile above at each step's start time; t0 is the time of the
+ * first step.  Returns the time after the last step. */
+double orc_run_scheduled(const orc_problem *p, double *m, int64_t nsteps, double dt, double t0,
+                         double t_start, double t_decay, double t_stop)
+{
+    const size_t N = (size_t)p->nx * p->ny * p->nz;
+    double *h = (double *)malloc(sizeof(double) * 3 * N);
+    orc_problem q = *p;
+    q.hext = h;
+    double t = t0;
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const double sc = orc_field_scale(t, t_start, t_decay, t_stop);
+        for (size_t i = 0; i < 3 * N; ++i) h[i] = sc * p->hext[i];
+        orc_step(&q, m, dt, NULL);
+        t += dt;
+    }
+    free(h);
+    return t;
+}
+
+/* Loss of a final state against a target: 1/2 sum over all 3N components of
+ * (m - t)^2 (the mismatch the gradient of the rollout is taken for). */
+double orc_loss(const double *m, const double *t, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = m[i] - t[i];
+        s += d * d;
+    }
+    return 0.5 * s;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Explicit Runge-Kutta steps of the same right-hand side f (fixed-step     */
 /* members of the Runge-Kutta family that adaptive time steps, named as      */
 /* future work in Sec. 6, build on).  With the Butcher tableau (A, b) of s   */
