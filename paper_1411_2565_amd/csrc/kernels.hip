@@ -363,8 +363,12 @@ __global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
 // kz > Pz/2.  Compensated form: each of the six real dot products of three
 // terms is accumulated error-free (fma products, two-sum) and rounded once.
 // ------------------------------------------------------------------------
+// Contraction is off in both helpers: an fma formed from a product and a
+// later sum would make the two-sum act on unrounded products, and the
+// correction term would then count each product's rounding twice.
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 {
+#pragma clang fp contract(off)
     s = a + b;
     const float bb = s - a;
     e = (a - (s - bb)) + (b - bb);
@@ -372,6 +376,7 @@ __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e)
 
 __device__ __forceinline__ float dot3_comp(float k0, float x0, float k1, float x1, float k2, float x2)
 {
+#pragma clang fp contract(off)
     // Dot2 (Ogita, Rump, Oishi 2005): p + sum of all rounding errors
     float p = k0 * x0;
     float s = fmaf(k0, x0, -p);
