@@ -81,9 +81,10 @@ def calibration_copy(nbytes=1 << 30, reps=3):
 
 
 def kernel_bytes(n, P):
-    """Algorithmic HBM bytes per launch of each kernel (FP32 data, complex64
-    spectra, each array read or written once; the tensor spectrum is the
-    real octant, 6 floats per stored frequency)."""
+    """HBM bytes per launch of each kernel as implemented (FP32 data,
+    complex64 spectra, each array read or written once; the tensor spectrum
+    is the real octant, 6 floats per stored frequency).  The x-inverse writes
+    H_demag and the local kernel reads it back."""
     nx, ny, nz = n
     Px, Py, Pz = P
     Hx = Px // 2 + 1
@@ -96,6 +97,28 @@ def kernel_bytes(n, P):
     k = 4 * 6 * Hx * Hy * Hz
     return {"xfwd": m + s1, "yfwd": s1 + s2, "zconv": 2 * s2 + k, "yinv": s2 + s1,
             "xinv": s1 + m, "local": 3 * m}
+
+
+def model_bytes(n, P):
+    """Algorithmic HBM bytes of one step: the same passes with the x-inverse
+    and the local update counted as one pass (S1 read, m read, m written),
+    i.e. without the H_demag round trip -- 734.15 MB at 256x256x32."""
+    kb = kernel_bytes(n, P)
+    nx, ny, nz = n
+    m = 4 * 3 * nx * ny * nz
+    return kb["xfwd"] + kb["yfwd"] + kb["zconv"] + kb["yinv"] + (kb["xinv"] - m) + 2 * m
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def padded(n):
@@ -125,6 +148,7 @@ def cpu_baseline(w, m0, target_s=12.0):
     P.step_cells(m0, cells, w.dt)
     el = time.perf_counter() - t
     return {"value": ncell / el, "unit": "cell-steps/s", "cores": oracle.threads(), "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": (f"one FP64 Euler step (direct-sum Newell demag over all {w.N} source cells + "
                        f"exchange/anisotropy/Zeeman + LLG) at {ncell} randomly sampled cells of the "
                        f"{w.n[0]}x{w.n[1]}x{w.n[2]} block; {el:.1f} s; tensor table build "
@@ -147,7 +171,7 @@ def cpu_full_steps():
         el = (time.perf_counter() - t) / reps
         rows.append({"workload": w.name, "cells": w.N, "s_per_step": float(f"{el:.4g}"),
                      "cell_steps_per_s": w.N / el})
-    return {"kind": "oracle", "cores": oracle.threads(), "rows": rows}
+    return {"kind": "oracle", "cores": oracle.threads(), "cpu": cpu_model(), "rows": rows}
 
 
 def adjoint_ratio(binding, T=2000):
@@ -156,7 +180,7 @@ def adjoint_ratio(binding, T=2000):
     L2 loss to the target pattern, sqrt(T) checkpoints."""
     import torch
     from paper_1411_2565_amd import workloads
-    from paper_1411_2565_amd.rollout import rollout
+    from paper_1411_2565_amd.rollout import l2_loss, rollout
     w = workloads.FILM_128x128x4
     m0, ms, h, t = workloads.adjoint_inputs(w)
     dev = torch.device("cuda", 0)
@@ -171,7 +195,7 @@ def adjoint_ratio(binding, T=2000):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         mT = rollout(m0g, hg, msg, sim, T, w.dt)
-        loss = 0.5 * ((mT - tgt) ** 2).sum()
+        loss = l2_loss(mT, tgt, sim)  # FP64 reduction on the GPU
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         loss.backward()
@@ -223,13 +247,63 @@ def batch_rate(binding, steps=5000, single_steps=200):
             sim.step(st, single_steps, w0.dt)
         torch.cuda.synchronize()
         ts = time.perf_counter() - t0
+        # the same films one by one, each replaying its own captured graphs
+        for sim, st in zip(sims, states):
+            sim.step(st, 64, w0.dt, binding.MM_F_GRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for sim, st in zip(sims, states):
+            sim.step(st, single_steps, w0.dt, binding.MM_F_GRAPH)
+        torch.cuda.synchronize()
+        tsg = time.perf_counter() - t0
         for sim in sims:
             sim.close()
     return {"workload": f"64 films, {cells} cells in all, 4x4x3 nm, dt=5e-14",
             "batched_cell_steps_per_s": cells * steps / tb, "batched_us_per_step": round(1e6 * tb / steps, 1),
             "one_by_one_cell_steps_per_s": cells * single_steps / ts,
             "one_by_one_us_per_step": round(1e6 * ts / single_steps, 1),
-            "speedup": round((cells * steps / tb) / (cells * single_steps / ts), 2)}
+            "one_by_one_graph_us_per_step": round(1e6 * tsg / single_steps, 1),
+            "speedup": round((cells * steps / tb) / (cells * single_steps / ts), 2),
+            "speedup_vs_graph_one_by_one": round((cells * steps / tb) / (cells * single_steps / tsg), 2)}
+
+
+def compensated_leg(binding, w, m0, steps=1000, timed_steps_n=300, crop_stride=8):
+    """Plain against compensated (Dot2) spectral multiply on the benchmark
+    block: microseconds per step of each, and the error of H_demag against
+    the FP64 oracle's direct sum on a subsample of the centred 64x64x8
+    crop of observers (x, y in [96, 160), z in [12, 20); every
+    crop_stride-th cell) at step 0 and after `steps` steps of each form."""
+    import numpy as np
+    import torch
+    import oracle
+    nx, ny, nz = w.n
+    z, y, x = np.meshgrid(np.arange(12, 20), np.arange(96, 160), np.arange(96, 160), indexing="ij")
+    obs = ((z * ny + y) * nx + x).ravel()[::crop_stride]
+    P = oracle.Problem(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, device=0)
+    out = {"workload": f"block {nx}x{ny}x{nz}, dt={w.dt}", "observers": int(obs.size),
+           "crop": "x,y in [96,160), z in [12,20), every %d-th cell" % crop_stride, "steps": steps}
+
+    def err(m):
+        Hd = sim.heff(m, binding.MM_T_DEMAG).cpu().double().numpy().reshape(3, -1)[:, obs]
+        ref = P.demag_observers(m.cpu().double().numpy(), obs)
+        return {"rel_l2": float(np.linalg.norm(Hd - ref) / np.linalg.norm(ref)),
+                "cell_max": float(np.abs(Hd - ref).max() / np.abs(ref).max())}
+
+    for name, comp in (("plain", 0), ("compensated", 1)):
+        binding.mm_set_compensated(sim.ctx, comp)
+        m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+        e0 = err(m)
+        sim.step(m, steps, w.dt)
+        sim.sync()
+        e1 = err(m)
+        sim.step(m, 20, w.dt)
+        t = timed_steps(sim, m, timed_steps_n, w.dt, 0)
+        out[name] = {"us_per_step": round(1e6 * t / timed_steps_n, 1), "h_demag_error_step0": e0,
+                     f"h_demag_error_step{steps}": e1}
+    sim.sync()
+    sim.close()
+    return out
 
 
 # Table 1 of the paper: ms per Euler step on an AMD Radeon HD 7970 GHz
@@ -402,12 +476,15 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=300,
-                    help="untimed steps first: the GPU ramps its clocks over the first ~100-300 steps of a burst")
-    ap.add_argument("--profile-steps", type=int, default=200,
-                    help="steps of the per-kernel event-timed region")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed steps right before the timed region")
+    ap.add_argument("--settle-steps", type=int, default=300,
+                    help="untimed steps before the warm-up: the GPU ramps its clocks over the first "
+                         "~100-300 steps of a burst")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--compensated", action="store_true", help="time the compensated spectral multiply")
+    ap.add_argument("--compensated", action="store_true",
+                    help="run the headline timing with the compensated spectral multiply")
+    ap.add_argument("--no-compensated-leg", action="store_true",
+                    help="skip the plain-vs-compensated timing and crop errors")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
     ap.add_argument("--sweep", action="store_true",
@@ -442,27 +519,25 @@ def main():
     t_build = time.perf_counter() - t
     m = torch.tensor(m0, dtype=torch.float32, device=dev)
 
-    print(f"bench: warmup {args.warmup} steps", file=sys.stderr, flush=True)
+    print(f"bench: {args.settle_steps} settle + {args.warmup} warm-up steps", file=sys.stderr, flush=True)
+    sim.step(m, args.settle_steps, w.dt, flags)
     sim.step(m, args.warmup, w.dt, flags)
     sim.sync()
 
+    # the timed region; every kernel's dispatch records its own start and
+    # stop events on the launch stream (per-kernel durations of this region)
     print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
+    binding.mm_kernel_timing(sim.ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(m, args.steps, w.dt, flags)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    sim.sync()
-    ms_step = 1e3 * el / max(args.steps, 1)
-    value = w.N * args.steps / el
-
-    # per-kernel durations from HIP events on the launch stream
-    print(f"bench: per-kernel event timing over {args.profile_steps} steps", file=sys.stderr, flush=True)
-    binding.mm_kernel_timing(sim.ctx, True)
-    sim.step(m, args.profile_steps, w.dt, flags)
     times = binding.mm_kernel_times(sim.ctx)
     binding.mm_kernel_timing(sim.ctx, False)
     sim.sync()
+    ms_step = 1e3 * el / max(args.steps, 1)
+    value = w.N * args.steps / el
     P = tuple(padded(v) for v in w.n)
     kb = kernel_bytes(w.n, P)
     kernels = {}
@@ -472,10 +547,15 @@ def main():
                       "GBps": round(kb[k] / (avg_us * 1e-6) / 1e9, 1) if cnt else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     ach = kernels[dom]["GBps"]
-    step_bytes = sum(kb.values())
+    step_bytes_impl = sum(kb.values())
+    step_bytes = model_bytes(w.n, P)
 
     sim.close()
     copy_bw = copy_bandwidth()
+    comp = None
+    if not args.no_compensated_leg:
+        print("bench: plain vs compensated spectral multiply", file=sys.stderr, flush=True)
+        comp = compensated_leg(binding, w, m0)
     adj = None
     if not args.no_adjoint:
         print("bench: adjoint/forward ratio on the 128x128x4 film", file=sys.stderr, flush=True)
@@ -521,6 +601,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
+        "settle_steps": args.settle_steps,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
@@ -535,6 +616,9 @@ def main():
         "cpu_baseline": cpu,
         "cpu_full_steps": cpu_full,
         "step_bytes": step_bytes,
+        "step_bytes_impl": step_bytes_impl,
+        "step_hbm_frac_impl": round(step_bytes_impl / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "compensated": comp,
         "copy_GBps": copy_bw,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
         "kernels": kernels,

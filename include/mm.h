@@ -129,10 +129,36 @@ mm_status mm_set_ms_map(mm_ctx *c, const float *ms_dev);
 /* Uniform external field (Sec. 2, H_extern), A/m. */
 mm_status mm_set_hext(mm_ctx *c, const double h[3]);
 
-/* Per-cell external field map (3N floats [3][nz][ny][nx], device, A/m),
- * copied into the workspace on the stream; NULL returns to the uniform
- * field. */
+/* Per-cell external field map (Sec. 2, H_extern of eq. (2) given cell by
+ * cell; 3N floats [3][nz][ny][nx], device, A/m), copied into the workspace
+ * on the stream; NULL returns to the uniform field. */
 mm_status mm_set_hext_map(mm_ctx *c, const float *h_dev);
+
+/* Time-dependent external field.  The paper's input file (Sec. 5) gives the
+ * external field with a startTime, a decayTime and a stopTime; the profile
+ * between them is not stated and is read here as
+ *     s(t) = 0                              t <  t_start
+ *            1                              t_start <= t <= t_decay
+ *            (t_stop - t)/(t_stop - t_decay) t_decay < t < t_stop
+ *            0                              t >= t_stop
+ * and multiplies the whole external field (uniform or map).  sched =
+ * {t_start, t_decay, t_stop} in seconds, finite, t_start <= t_decay <=
+ * t_stop (MM_EINVAL otherwise); NULL returns to the constant field.  The
+ * time lives on the device (mm_set_time): each Euler step of mm_step_llg
+ * evaluates the field at the current time t_n and advances it by dt in FP64
+ * (t_{n+1} = t_n + dt), also inside captured graphs, so replays continue the
+ * clock.  mm_compute_heff and mm_reduce use the field at the current time.
+ * While a schedule is set, Runge-Kutta steps (MM_F_HEUN, MM_F_RK4),
+ * mm_step_adaptive, mm_forward_store and mm_adjoint_step return MM_EUNSUP. */
+mm_status mm_set_field_schedule(mm_ctx *c, const double sched[3]);
+
+/* Set the device clock of the time-dependent field to t (s), enqueued on the
+ * stream; mm_set_workspace sets it to 0. */
+mm_status mm_set_time(mm_ctx *c, double t);
+
+/* Read the device clock (the time of the next step) into *t; synchronises
+ * the stream. */
+mm_status mm_get_time(mm_ctx *c, double *t);
 
 /* Build the demag tensor spectrum for the geometry (Sec. 3: the convolution
  * kernel of the zero-padded FFT evaluation).  The cell-averaged tensor is
@@ -181,6 +207,18 @@ mm_status mm_step_llg(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, uint32
  *     E_anis  = Ku V sum (1 - (m . u)^2)
  *     E_zeeman = -mu0 V sum Ms m . h_ext */
 mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
+
+/* FP64 loss of a state against a target, the L2 mismatch
+ *     L = 1/2 sum over all 3N components (m - t)^2
+ * that the gradient of an Euler rollout (mm_adjoint_step) is taken for,
+ * written to out_dev (1 double, device).  When grad_dev is not NULL it
+ * receives dL/dm = m - t (3N floats, FP32; may not alias m or t).  Each
+ * block of the reduction adds a fixed run of 2048 consecutive values and the
+ * block sums are added in a fixed order, so the result is deterministic.
+ * Needs the workspace (its partial sums); the material and tensor are not
+ * used. */
+mm_status mm_reduce_loss(mm_ctx *c, const float *m_dev, const float *target_dev, double *out_dev,
+                         float *grad_dev);
 
 /* Use (on != 0) or stop using the compensated FP32 spectral multiply in every
  * demag evaluation of this context (mm_compute_heff, mm_reduce, steps and
@@ -237,7 +275,9 @@ mm_status mm_autotune(mm_ctx *c, const char *cache_path, int32_t choice_out[3]);
 mm_status mm_step_adaptive(mm_ctx *c, float *m_dev, double t_end, double *dt_io, double tol, uint32_t flags,
                            int64_t max_steps, int64_t *accepted, int64_t *rejected);
 
-/* Forward rollout that keeps what the adjoint needs: advances m_dev in place
+/* Forward rollout that keeps what the adjoint needs (the explicit Euler
+ * integration of eq. (3), Sec. 3, run as the first half of the gradient
+ * computation of mm_adjoint_step): advances m_dev in place
  * by nsteps Euler steps exactly as mm_step_llg does, and stores the state
  * entering step s in m_traj[s] and its demagnetising field in hd_traj[s]
  * (each nsteps * 3N floats, device, [s][3][nz][ny][nx]). */
@@ -267,10 +307,11 @@ enum {
 };
 
 /* Diagnostic timing: while enabled, every kernel launched by mm_step_llg and
- * mm_compute_heff is bracketed by two HIP events on the context's stream and
- * its duration is accumulated per kernel identifier.  Enabling clears the
- * totals.  Events serialise nothing that the single stream does not already
- * serialise. */
+ * mm_compute_heff records a start and a stop HIP event on the context's
+ * stream as part of its own dispatch, and its duration is accumulated per
+ * kernel identifier.  Enabling clears the totals.  Events serialise nothing
+ * that the single stream does not already serialise; the host waits for the
+ * stream only when 16384 event pairs are pending (and in mm_kernel_times). */
 mm_status mm_kernel_timing(mm_ctx *c, int enable);
 
 /* Synchronise the stream, fold pending event pairs into the totals and

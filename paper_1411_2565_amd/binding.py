@@ -78,6 +78,10 @@ def load():
         "mm_forward_store": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32, _P, _P],
         "mm_adjoint_step": [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_uint32],
         "mm_kernel_times": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+        "mm_set_field_schedule": [_P, ctypes.POINTER(ctypes.c_double)],
+        "mm_set_time": [_P, ctypes.c_double],
+        "mm_get_time": [_P, ctypes.POINTER(ctypes.c_double)],
+        "mm_reduce_loss": [_P, _P, _P, _P, _P],
     }
     sig.update({
         "mm_batch_create": [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_double,
@@ -206,6 +210,29 @@ def mm_reduce(ctx, m, out, N):
     import torch
     _check(ctx, load().mm_reduce(ctx, _dev(m, torch.float32, 3 * N, "m"), _dev(out, torch.float64, 8, "out")),
            "mm_reduce")
+
+
+def mm_reduce_loss(ctx, m, target, out, grad, N):
+    import torch
+    g = None if grad is None else _dev(grad, torch.float32, 3 * N, "grad")
+    _check(ctx, load().mm_reduce_loss(ctx, _dev(m, torch.float32, 3 * N, "m"),
+                                      _dev(target, torch.float32, 3 * N, "target"),
+                                      _dev(out, torch.float64, 1, "out"), g), "mm_reduce_loss")
+
+
+def mm_set_field_schedule(ctx, sched):
+    arr = None if sched is None else (ctypes.c_double * 3)(*map(float, sched))
+    _check(ctx, load().mm_set_field_schedule(ctx, arr), "mm_set_field_schedule")
+
+
+def mm_set_time(ctx, t):
+    _check(ctx, load().mm_set_time(ctx, float(t)), "mm_set_time")
+
+
+def mm_get_time(ctx):
+    t = ctypes.c_double()
+    _check(ctx, load().mm_get_time(ctx, ctypes.byref(t)), "mm_get_time")
+    return t.value
 
 
 def mm_sync(ctx):
@@ -470,6 +497,28 @@ class Sim:
         out = torch.empty(8, dtype=torch.float64, device=self.device)
         mm_reduce(self.ctx, m, out, self.N)
         return out
+
+    def loss(self, m, target, grad=False):
+        """FP64 loss 1/2 sum (m - target)^2 on the GPU: a 1-element float64
+        tensor, and with grad=True also dL/dm = m - target (FP32)."""
+        import torch
+        self._s()
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        g = torch.empty(self.shape, dtype=torch.float32, device=self.device) if grad else None
+        mm_reduce_loss(self.ctx, m, target, out, g, self.N)
+        return (out, g) if grad else out
+
+    def set_field_schedule(self, sched):
+        """(t_start, t_decay, t_stop) in s, or None for a constant field."""
+        mm_set_field_schedule(self.ctx, sched)
+
+    def set_time(self, t):
+        self._s()
+        mm_set_time(self.ctx, t)
+
+    def time(self):
+        self._s()
+        return mm_get_time(self.ctx)
 
     def tensor_table(self):
         import torch

@@ -52,10 +52,15 @@ struct mm_ctx {
     size_t ws_bytes = 0;
     // workspace layout (byte offsets)
     size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_rk = 0, o_T = 0, o_tA = 0, o_tB = 0;
-    size_t o_ms = 0, o_h = 0, o_part = 0, o_flag = 0, o_adj = 0, total = 0;
+    size_t o_ms = 0, o_h = 0, o_part = 0, o_lpart = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
     bool vacuum = false;       // the Ms map holds vacuum cells (Ms = 0)
     int tune[3] = {0, 0, 0};   // launch-shape variants of the x, y and z passes
+    // time-dependent external field: profile times, and which slot of the
+    // device clock holds the time of the next step (toggled per Euler step)
+    bool sched = false;
+    double sched_t[3] = {0, 0, 0};
+    int tslot = 0;
     std::string err;
     // captured step chunks (MM_F_GRAPH): kernel arguments (state pointer,
     // material, fields, maps, dt) are baked in, so every setter drops them
@@ -65,6 +70,7 @@ struct mm_ctx {
         double dt;
         uint32_t flags;
         hipStream_t stream;
+        int tslot;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -156,6 +162,7 @@ void layout(mm_ctx *c)
     c->o_ms = cv.take(sizeof(float) * N);
     c->o_h = cv.take(sizeof(float) * 3 * N);
     c->o_part = cv.take(sizeof(double) * 8 * mmk::kEnergyBlocks + sizeof(double) * 8);
+    c->o_lpart = cv.take(sizeof(double) * (size_t)mmk::loss_partials(3 * (long long)N));
     c->o_flag = cv.take(256);
     c->o_adj = cv.take(sizeof(float) * 6 * N);  // adjoint: g_H and the local part of lambda
     // region shared by the step buffers and the tensor-build temporaries
@@ -211,7 +218,9 @@ template <typename F>
 mm_status timed(mm_ctx *c, int kernel, const char *what, F &&launch)
 {
     if (!c->timing) return hipcheck(c, launch(), what);
-    if (c->pending.size() >= 2048) MM_TRY(drain_timing(c));
+    // folding needs a synchronisation: only when many pairs are pending, so a
+    // timed region of a few thousand launches runs without one
+    if (c->pending.size() >= 16384) MM_TRY(drain_timing(c));
     hipEvent_t a = take_event(c), b = take_event(c);
     if (!a || !b) return fail(c, MM_EHIP, "hipEventCreate failed");
     mmk::set_launch_events(a, b);
@@ -236,6 +245,9 @@ mm_status need_ws(mm_ctx *c)
 
 mm_status set_device(mm_ctx *c) { return hipcheck(c, hipSetDevice(c->device), "hipSetDevice"); }
 
+// the device clock of the time-dependent field: two FP64 slots in the flag block
+double *clock_ptr(const mm_ctx *c) { return reinterpret_cast<double *>(c->at<char>(c->o_flag) + 192); }
+
 mmk::LocalParams local_params(const mm_ctx *c)
 {
     mmk::LocalParams p{};
@@ -256,6 +268,12 @@ mmk::LocalParams local_params(const mm_ctx *c)
     p.c2 = (float)(m.alpha * c1);
     p.stage_kstore = -1;  // no stored slopes unless a tableau asks for them
     p.stage_nprev = 0;
+    p.sched = c->sched ? 1 : 0;
+    p.tslot = c->tslot;
+    p.clk = c->ws ? clock_ptr(c) : nullptr;
+    p.t_start = c->sched_t[0];
+    p.t_decay = c->sched_t[1];
+    p.t_stop = c->sched_t[2];
     return p;
 }
 
@@ -377,7 +395,9 @@ mm_status mm_set_workspace(mm_ctx *c, void *dev_ptr, size_t bytes)
     c->ms_map = false;
     c->h_map = false;
     MM_TRY(set_device(c));
-    return hipcheck(c, hipMemsetAsync(c->at<int>(c->o_flag), 0, sizeof(int), c->stream), "clear flag");
+    MM_TRY(hipcheck(c, hipMemsetAsync(c->at<int>(c->o_flag), 0, sizeof(int), c->stream), "clear flag"));
+    c->tslot = 0;
+    return hipcheck(c, mmk::launch_set_clock(clock_ptr(c), 0.0, c->stream), "set clock");
 }
 
 mm_status mm_set_material(mm_ctx *c, const mm_material *m)
@@ -452,6 +472,43 @@ mm_status mm_set_hext_map(mm_ctx *c, const float *h)
     c->h_map = true;
     c->drop_graphs();
     return MM_OK;
+}
+
+mm_status mm_set_field_schedule(mm_ctx *c, const double sched[3])
+{
+    if (!c) return MM_EINVAL;
+    if (!sched) {
+        c->sched = false;
+        c->drop_graphs();
+        return MM_OK;
+    }
+    for (int i = 0; i < 3; ++i)
+        if (!std::isfinite(sched[i])) return fail(c, MM_EINVAL, "schedule times must be finite");
+    if (!(sched[0] <= sched[1] && sched[1] <= sched[2]))
+        return fail(c, MM_EINVAL, "schedule needs t_start <= t_decay <= t_stop");
+    for (int i = 0; i < 3; ++i) c->sched_t[i] = sched[i];
+    c->sched = true;
+    c->drop_graphs();
+    return MM_OK;
+}
+
+mm_status mm_set_time(mm_ctx *c, double t)
+{
+    if (!c) return MM_EINVAL;
+    if (!std::isfinite(t)) return fail(c, MM_EINVAL, "time must be finite");
+    MM_TRY(need_ws(c));
+    MM_TRY(set_device(c));
+    return hipcheck(c, mmk::launch_set_clock(clock_ptr(c), t, c->stream), "set clock");
+}
+
+mm_status mm_get_time(mm_ctx *c, double *t)
+{
+    if (!c) return MM_EINVAL;
+    if (!t) return fail(c, MM_EINVAL, "t is NULL");
+    MM_TRY(need_ws(c));
+    MM_TRY(set_device(c));
+    MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "clock sync"));
+    return hipcheck(c, hipMemcpy(t, clock_ptr(c) + c->tslot, sizeof(double), hipMemcpyDeviceToHost), "read clock");
 }
 
 mm_status mm_tensor_table(mm_ctx *c, double *tab)
@@ -544,9 +601,12 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
         }
         return MM_OK;
     }
+    p.dt64 = dt;
     for (int64_t s = 0; s < nsteps; ++s) {
         float *Hd = nullptr;
         MM_TRY(demag(c, src(s), comp, &Hd, hd(s)));
+        p.tslot = c->tslot;
+        if (c->sched) c->tslot ^= 1;  // this step's kernel writes the next step's time
         MM_TRY(timed(c, MM_K_LOCAL, "llg step", [&] {
             return mmk::launch_local(c->g, p, src(s), Hd, ms_map_ptr(c), h_map_ptr(c), MM_T_ALL, 1, (float)dt,
                                      renorm, dst(s), nullptr, flag, c->stream);
@@ -651,11 +711,12 @@ mm_status enqueue_steps(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t
 mm_status graph_for(mm_ctx *c, float *m, int64_t n, double dt, uint32_t flags, hipGraphExec_t *out)
 {
     for (auto &e : c->graphs)
-        if (e.m == m && e.n == n && e.dt == dt && e.flags == flags && e.stream == c->stream) {
+        if (e.m == m && e.n == n && e.dt == dt && e.flags == flags && e.stream == c->stream && e.tslot == c->tslot) {
             *out = e.exec;
             return MM_OK;
         }
     const bool was_timing = c->timing;
+    const int tslot0 = c->tslot;
     c->timing = false;
     MM_TRY(hipcheck(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture"));
     mm_status st = enqueue_steps(c, m, n, dt, flags);
@@ -671,7 +732,8 @@ mm_status graph_for(mm_ctx *c, float *m, int64_t n, double dt, uint32_t flags, h
     const hipError_t e_inst = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     MM_TRY(hipcheck(c, e_inst, "instantiate graph"));
-    c->graphs.push_back({m, n, dt, flags, c->stream, exec});
+    c->tslot = tslot0;  // n is even: a replay leaves the clock slot where it found it
+    c->graphs.push_back({m, n, dt, flags, c->stream, tslot0, exec});
     *out = exec;
     return MM_OK;
 }
@@ -687,6 +749,8 @@ mm_status mm_step_llg(mm_ctx *c, float *m, int64_t nsteps, double dt, uint32_t f
     if (!c) return MM_EINVAL;
     const uint32_t step_flags = flags & ~uint32_t(MM_F_GRAPH);
     MM_TRY(check_step_args(c, m, nsteps, dt, step_flags));
+    if (c->sched && (step_flags & (MM_F_HEUN | MM_F_RK4)))
+        return fail(c, MM_EUNSUP, "a time-dependent field is applied by Euler steps only");
     MM_TRY(set_device(c));
     if (!(flags & MM_F_GRAPH)) return enqueue_steps(c, m, nsteps, dt, step_flags);
     if (!c->stream) return fail(c, MM_EINVAL, "MM_F_GRAPH needs a non-null stream (capture is not allowed on it)");
@@ -716,6 +780,7 @@ mm_status mm_step_adaptive(mm_ctx *c, float *m, double t_end, double *dt_io, dou
     if (flags & ~uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED | MM_F_HEUN | MM_F_BS23 | MM_F_DP54))
         return fail(c, MM_EINVAL, "unsupported flag bits 0x%x for adaptive steps", flags);
     MM_TRY(check_step_args(c, m, 0, *dt_io, flags & uint32_t(MM_F_NO_RENORM | MM_F_COMPENSATED)));
+    if (c->sched) return fail(c, MM_EUNSUP, "a time-dependent field is applied by Euler steps only");
     MM_TRY(set_device(c));
     const Pair pair = heun ? Pair::HeunEuler : (bs23 ? Pair::BS23 : Pair::DP54);
     const int q = heun ? 1 : (bs23 ? 2 : 4);  // order of the lower member
@@ -893,6 +958,7 @@ mm_status mm_forward_store(mm_ctx *c, float *m, int64_t nsteps, double dt, uint3
     MM_TRY(check_step_args(c, m, nsteps, dt, flags));
     if (flags & (MM_F_HEUN | MM_F_RK4))
         return fail(c, MM_EUNSUP, "the stored replay and the adjoint cover the Euler step only");
+    if (c->sched) return fail(c, MM_EUNSUP, "the stored replay and the adjoint cover constant fields only");
     if (c->ms_map && c->vacuum) return fail(c, MM_EUNSUP, "the adjoint covers samples without vacuum cells");
     if (nsteps > 0 && (!m_traj || !hd_traj || !aligned16(m_traj) || !aligned16(hd_traj)))
         return fail(c, MM_EINVAL, "trajectory buffers must be 16-byte aligned device pointers");
@@ -914,6 +980,7 @@ mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float 
     if (!c) return MM_EINVAL;
     MM_TRY(check_step_args(c, m_n, 1, dt, flags));
     if (flags & (MM_F_HEUN | MM_F_RK4)) return fail(c, MM_EUNSUP, "the adjoint covers the Euler step only");
+    if (c->sched) return fail(c, MM_EUNSUP, "the adjoint covers constant fields only");
     if (c->ms_map && c->vacuum) return fail(c, MM_EUNSUP, "the adjoint covers samples without vacuum cells");
     if (!hd_n || !lam || !aligned16(hd_n) || !aligned16(lam))
         return fail(c, MM_EINVAL, "hd_n and lam must be 16-byte aligned device pointers");
@@ -962,9 +1029,28 @@ mm_status mm_reduce(mm_ctx *c, const float *m, double *out)
     e.V = c->d[0] * c->d[1] * c->d[2];
     e.mu0 = kMu0;
     e.terms = MM_T_ALL;
+    e.sched = c->sched ? 1 : 0;
+    e.tslot = c->tslot;
+    e.clk = clock_ptr(c);
+    e.t_start = c->sched_t[0];
+    e.t_decay = c->sched_t[1];
+    e.t_stop = c->sched_t[2];
     return hipcheck(c, mmk::launch_energy(c->g, e, m, Hd, ms_map_ptr(c), h_map_ptr(c), c->at<double>(c->o_part), out,
                                           c->stream),
                     "energy");
+}
+
+mm_status mm_reduce_loss(mm_ctx *c, const float *m, const float *target, double *out, float *grad)
+{
+    if (!c) return MM_EINVAL;
+    if (!m || !target || !out || !aligned16(m) || !aligned16(target) || !aligned16(out))
+        return fail(c, MM_EINVAL, "m, target and out must be 16-byte aligned device pointers");
+    if (grad && !aligned16(grad)) return fail(c, MM_EINVAL, "grad must be 16-byte aligned");
+    if (grad && (grad == m || grad == target)) return fail(c, MM_EINVAL, "grad may not alias m or target");
+    MM_TRY(need_ws(c));
+    MM_TRY(set_device(c));
+    return hipcheck(c, mmk::launch_loss(m, target, 3 * c->g.N, grad, c->at<double>(c->o_lpart), out, c->stream),
+                    "loss");
 }
 
 mm_status mm_kernel_timing(mm_ctx *c, int enable)

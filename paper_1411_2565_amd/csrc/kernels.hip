@@ -569,6 +569,18 @@ __global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(Batch<XinvDesc
 // Free (Neumann) boundaries: a missing neighbour contributes nothing.
 // V cells along x per thread (4 with 16-byte accesses when nx % 4 == 0).
 // ------------------------------------------------------------------------
+// Profile of the time-dependent external field (the field record of Sec. 5
+// gives a start, a decay and a stop time; read as off, full strength, linear
+// decay to zero, off).  FP64, so the switching times are decided exactly as
+// on any other FP64 host.
+__device__ __forceinline__ double field_scale(double t, double t_start, double t_decay, double t_stop)
+{
+    if (t < t_start) return 0.0;
+    if (t <= t_decay) return 1.0;
+    if (t >= t_stop) return 0.0;
+    return (t_stop - t) / (t_stop - t_decay);
+}
+
 template <int V>
 struct VecT;
 template <>
@@ -638,6 +650,14 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     const float *__restrict__ h_map = D.h_map;
     float *__restrict__ out_m = D.m_out;
     float *__restrict__ out_h = D.h_out;
+    // time-dependent field: every block reads this step's time from one
+    // clock slot; an Euler step writes the next step's time into the other
+    float hsc = 1.f;
+    if (p.sched) {
+        const double t = p.clk[p.tslot];
+        hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
+        if (MODE == 1 && blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
+    }
     const long long i0 = ((long long)local_block(blockIdx.x, D.perm_q) * kThreads + threadIdx.x) * V;
     if (i0 >= g.N) return;
     const long long N = g.N;
@@ -761,14 +781,15 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
                 float e[V];
                 vload<V>(h_map + c * N + i0, e);
 #pragma unroll
-                for (int j = 0; j < V; ++j) h[c][j] += e[j];
+                for (int j = 0; j < V; ++j) h[c][j] = fmaf(hsc, e[j], h[c][j]);
             }
         } else {
+            const float e0 = hsc * D.h0, e1 = hsc * D.h1, e2 = hsc * D.h2;
 #pragma unroll
             for (int j = 0; j < V; ++j) {
-                h[0][j] += D.h0;
-                h[1][j] += D.h1;
-                h[2][j] += D.h2;
+                h[0][j] += e0;
+                h[1][j] += e1;
+                h[2][j] += e2;
             }
         }
     }
@@ -1082,6 +1103,9 @@ __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, cons
     __shared__ double red[kEq][kThreads];
     double acc[kEq] = {0, 0, 0, 0, 0, 0, 0, 0};
     const long long N = g.N;
+    // the external field at the clock's time, scaled as in the step (FP32
+    // scale, so the energy sees the field the step applies)
+    const double hsc = p.sched ? (double)(float)field_scale(p.clk[p.tslot], p.t_start, p.t_decay, p.t_stop) : 1.0;
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < N;
          i += (long long)gridDim.x * kThreads) {
         const double mx = m[i], my = m[N + i], mz = m[2 * N + i];
@@ -1112,7 +1136,7 @@ __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, cons
                 h1 = h_map[N + i];
                 h2 = h_map[2 * N + i];
             }
-            acc[3] += ms * (mx * h0 + my * h1 + mz * h2);
+            acc[3] += hsc * ms * (mx * h0 + my * h1 + mz * h2);
         }
         acc[4] += mx;
         acc[5] += my;
@@ -1803,6 +1827,87 @@ hipError_t launch_tensor_spectrum(const Geo &g, const double *T, double *tmpA, d
         hipLaunchKernelGGL(k_pack, dim3((unsigned)((tot + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, g,
                            tmpA, c, scale, K);
     }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// Clock of the time-dependent external field: both slots set to t.  A kernel
+// rather than a host copy, so it is ordered on the stream like the steps.
+// ------------------------------------------------------------------------
+__global__ void k_set_clock(double *clk, double t)
+{
+    if (threadIdx.x < 2) clk[threadIdx.x] = t;
+}
+
+hipError_t launch_set_clock(double *clk, double t, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(64), 0, s, clk, t);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------
+// FP64 loss L = 1/2 sum_i (m_i - t_i)^2 (the L2 mismatch of a final state
+// to a target) and its gradient m - t.  Block b takes the kLossChunk values
+// [b kLossChunk, (b+1) kLossChunk): each thread adds its values in order,
+// the wavefront adds across lanes by shuffles, then the 4 wavefronts' sums
+// are added in order.  The difference of two FP32 values is exact in FP64.
+// ------------------------------------------------------------------------
+constexpr int kLossItems = (int)(kLossChunk / kThreads);
+static_assert(kLossChunk % kThreads == 0, "loss chunk is whole rows of the block");
+
+__device__ __forceinline__ double block_sum256(double v, double *lds)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < kThreads / 64; ++w) r += lds[w];
+    return r;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ m, const float *__restrict__ t,
+                                                   long long n, float *__restrict__ grad,
+                                                   double *__restrict__ partials)
+{
+    __shared__ double red[kThreads / 64];
+    const long long base = (long long)blockIdx.x * kLossChunk + threadIdx.x;
+    float a[kLossItems], b[kLossItems];
+#pragma unroll
+    for (int k = 0; k < kLossItems; ++k) {
+        const long long i = base + (long long)k * kThreads;
+        a[k] = i < n ? m[i] : 0.f;
+        b[k] = i < n ? t[i] : 0.f;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kLossItems; ++k) {
+        const double d = (double)a[k] - (double)b[k];
+        acc = fma(d, d, acc);
+        const long long i = base + (long long)k * kThreads;
+        if (grad && i < n) grad[i] = a[k] - b[k];
+    }
+    const double r = block_sum256(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kThreads) void k_loss_final(const double *__restrict__ partials, long long nblk,
+                                                         double *__restrict__ out)
+{
+    __shared__ double red[kThreads / 64];
+    double acc = 0.0;
+    for (long long b = threadIdx.x; b < nblk; b += kThreads) acc += partials[b];
+    const double r = block_sum256(acc, red);
+    if (threadIdx.x == 0) out[0] = 0.5 * r;
+}
+
+hipError_t launch_loss(const float *m, const float *t, long long n, float *grad, double *partials, double *out,
+                       hipStream_t s)
+{
+    const long long nb = loss_partials(n);
+    if (n < 1 || nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_loss, dim3((unsigned)nb), dim3(kThreads), 0, s, m, t, n, grad, partials);
+    hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(kThreads), 0, s, partials, nb, out);
     return hipGetLastError();
 }
 

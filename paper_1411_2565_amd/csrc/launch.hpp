@@ -34,6 +34,12 @@ struct LocalParams {
     // stage_ap[jj] kbuf[jj]; stage_kstore >= 0 stores this stage's k there
     float stage_ap[6];
     int stage_nprev, stage_kstore;
+    // time-dependent external field (sched != 0): the field is scaled by
+    // field_scale(t) with t = clk[tslot]; an Euler step (mode 1) also writes
+    // clk[tslot ^ 1] = t + dt64 for the next step
+    int sched, tslot;
+    double *clk;
+    double t_start, t_decay, t_stop, dt64;
 };
 
 // Per-sample arguments of one pass.  A launch processes up to kMaxBatch
@@ -92,6 +98,10 @@ struct EnergyParams {
     double V;           // cell volume
     double mu0;
     uint32_t terms;
+    // time-dependent external field as in LocalParams (read only)
+    int sched, tslot;
+    const double *clk;
+    double t_start, t_decay, t_stop;
 };
 
 constexpr int kEnergyBlocks = 512;
@@ -153,6 +163,18 @@ hipError_t launch_adj_b(const Geo &g, const LocalParams &p, const float *m, cons
 hipError_t launch_energy(const Geo &g, const EnergyParams &p, const float *m, const float *Hd,
                          const float *ms_map, const float *h_map, double *partials, double *out,
                          hipStream_t s);
+
+// device clock of the time-dependent field: clk[0] = clk[1] = t
+hipError_t launch_set_clock(double *clk, double t, hipStream_t s);
+
+// FP64 loss 1/2 sum_i (m_i - t_i)^2 over n values into out[0], and m - t
+// into grad (FP32) when grad is not null.  Each block reduces one chunk of
+// kLossChunk consecutive values into partials[b] (loss_partials(n) slots),
+// one block then adds the partials in block order: deterministic.
+constexpr long long kLossChunk = 2048;
+constexpr long long loss_partials(long long n) { return (n + kLossChunk - 1) / kLossChunk; }
+hipError_t launch_loss(const float *m, const float *t, long long n, float *grad, double *partials, double *out,
+                       hipStream_t s);
 
 // FP64 tensor build
 hipError_t launch_tensor_octant(const Geo &g, double dx, double dy, double dz, double *T, hipStream_t s);

@@ -68,3 +68,25 @@ class LLGRollout(torch.autograd.Function):
 def rollout(m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None):
     """m_T of a T-step Euler rollout, differentiable in m0, hext_map, ms_map."""
     return LLGRollout.apply(m0, hext_map, ms_map, sim, T, dt, flags, seg)
+
+
+class L2Loss(torch.autograd.Function):
+    """L = 1/2 sum (m - t)^2 reduced in FP64 on the GPU (mm_reduce_loss),
+    returned as a float64 scalar; the same kernel writes dL/dm = m - t, which
+    the backward hands on (times the incoming gradient)."""
+
+    @staticmethod
+    def forward(ctx, m, target, sim):
+        out, g = sim.loss(m.detach().contiguous(), target.detach().contiguous(), grad=True)
+        ctx.save_for_backward(g)
+        return out.reshape(())
+
+    @staticmethod
+    def backward(ctx, go):
+        (g,) = ctx.saved_tensors
+        return g * go.to(g.dtype), None, None
+
+
+def l2_loss(m, target, sim):
+    """FP64 GPU loss 1/2 sum (m - target)^2, differentiable in m."""
+    return L2Loss.apply(m, target, sim)

@@ -41,6 +41,8 @@ def test_byte_model_of_the_block_step():
     # the fused a5-a8 tail would not write H_demag and read it back: 2 x 25.17 MB
     h_round_trip = 2 * 4 * 3 * 256 * 256 * 32
     assert abs((sum(kb.values()) - h_round_trip) / 1e6 - 734.15) < 0.1
+    # the headline fraction of HBM peak is taken on that 734.15 MB model
+    assert abs(bench.model_bytes((256, 256, 32), (512, 512, 64)) / 1e6 - 734.15) < 0.1
 
 
 def test_measured_traffic_is_tied_to_the_sources():

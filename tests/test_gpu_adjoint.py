@@ -2,9 +2,16 @@
 torch.autograd.Function with sqrt(T) checkpointing) against the FP64 oracle's
 exact adjoint and against FP64 central differences of the oracle.
 
-Tolerances: GPU gradients (FP32 forward, FP32 adjoint) within 2e-4 relative
-L2 of the oracle's FP64 gradients over the full maps; directional
-derivatives within 1e-3 of FP64 central differences on sampled cells.
+The loss 1/2 sum |m_T - t|^2 is reduced in FP64 on the GPU (mm_reduce_loss).
+Tolerances, about ten times the errors observed on an MI355X: GPU gradients
+(FP32 forward, FP32 adjoint) within 5e-6 relative L2 of the oracle's FP64
+gradients over the full maps for horizons up to T = 100; directional
+derivatives within 1e-5 (median) and 1e-4 (max) of FP64 central
+differences on sampled cells.  The T = 2000 rollout of the gradient
+workload's material on a 32x32x4 film (sqrt(T) = 45-step checkpoint
+segments, the configured horizon) and the 128x128x4 workload geometry at
+T = 100 are checked the same way (the latter against stored oracle
+values, tests/golden/adjoint_film128x128x4_T100.npz).
 
 Paper: Zhu, arXiv:1411.2565, eqs. (2)-(3) and the Euler integration of
 Sec. 3; the adjoint is the exact transpose of that discrete step.
@@ -41,16 +48,16 @@ def film_analogue(n=(32, 32, 4)):
 
 def gpu_grads(gpu_lib, w, m0, ms, h, t, T, dt, seg=None, Ku=0.0, u=(1.0, 0.0, 0.0)):
     import torch
-    from paper_1411_2565_amd.rollout import rollout
+    from paper_1411_2565_amd.rollout import l2_loss, rollout
     sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=Ku, u=u, alpha=w.alpha)
     m0g = gpu(m0).requires_grad_(True)
     hg = gpu(h).requires_grad_(True)
     msg = gpu(ms).requires_grad_(True)
     mT = rollout(m0g, hg, msg, sim, T, dt, 0, seg)
-    loss = 0.5 * ((mT - gpu(t)) ** 2).sum()
+    loss = l2_loss(mT, gpu(t), sim)
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss), host(m0g.grad), host(hg.grad), host(msg.grad), sim
+    return float(loss.detach()), host(m0g.grad), host(hg.grad), host(msg.grad), sim
 
 
 @pytest.mark.parametrize("Ku", [0.0, 4e4])
@@ -65,10 +72,10 @@ def test_gpu_gradients_match_oracle_small(gpu_lib, Ku):
     lo, gmo, gho, gmso = P.adjoint(host(gpu(m0)), T, dt, host(gpu(t)))
     print(f"adjoint 24x16x3 Ku={Ku}: loss {loss:.6e} vs {lo:.6e}; rel L2 dm0 {rel(gm, gmo):.2e} "
           f"dh {rel(gh, gho):.2e} dMs {rel(gms, gmso):.2e}")
-    assert abs(loss - lo) < 1e-4 * lo
-    assert rel(gm, gmo) < 2e-4
-    assert rel(gh, gho) < 2e-4
-    assert rel(gms, gmso) < 2e-4
+    assert abs(loss - lo) < 1e-6 * lo
+    assert rel(gm, gmo) < 5e-6
+    assert rel(gh, gho) < 5e-6
+    assert rel(gms, gmso) < 5e-6
 
 
 def test_checkpointing_is_exact(gpu_lib):
@@ -116,8 +123,8 @@ def test_gradients_vs_fp64_central_differences(gpu_lib):
         errs.append(abs(ad - fd) / max(abs(fd), 1e-30))
     errs = np.array(errs)
     print(f"FD check 32x32x4 T=100: max rel err {errs.max():.2e}, median {np.median(errs):.2e}")
-    assert np.median(errs) < 1e-3
-    assert errs.max() < 1e-2
+    assert np.median(errs) < 1e-5
+    assert errs.max() < 1e-4
 
 
 def test_adjoint_workload_geometry_short_horizon(gpu_lib):
@@ -130,4 +137,43 @@ def test_adjoint_workload_geometry_short_horizon(gpu_lib):
     P = oracle.Problem(w.n, w.d, Ms=host(gpu(ms)), A=w.A, alpha=w.alpha, hext=host(gpu(h)))
     lo, gmo, gho, gmso = P.adjoint(host(gpu(m0)), T, w.dt, host(gpu(t)))
     print(f"adjoint 128x128x4 T=5: rel L2 dm0 {rel(gm, gmo):.2e} dh {rel(gh, gho):.2e} dMs {rel(gms, gmso):.2e}")
-    assert rel(gm, gmo) < 2e-4 and rel(gh, gho) < 2e-4 and rel(gms, gmso) < 2e-4
+    assert rel(gm, gmo) < 5e-6 and rel(gh, gho) < 5e-6 and rel(gms, gmso) < 5e-6
+
+
+def test_gradients_T2000_checkpointed_vs_oracle(gpu_lib):
+    """The configured horizon T = 2000 with sqrt(T) = 45-step checkpoint
+    segments, on a 32x32x4 film of the gradient workload's material, maps
+    and target at dt = 2e-14 (stable), against the oracle's FP64 adjoint
+    over the full maps."""
+    w, m0, ms, h, t = film_analogue((32, 32, 4))
+    T, dt = 2000, 2e-14
+    loss, gm, gh, gms, _ = gpu_grads(gpu_lib, w, m0, ms, h, t, T, dt)
+    P = oracle.Problem(w.n, w.d, Ms=host(gpu(ms)), A=w.A, alpha=w.alpha, hext=host(gpu(h)))
+    lo, gmo, gho, gmso = P.adjoint(host(gpu(m0)), T, dt, host(gpu(t)))
+    e = (rel(gm, gmo), rel(gh, gho), rel(gms, gmso))
+    print(f"adjoint 32x32x4 T=2000 (45-step segments): loss {loss:.9e} vs {lo:.9e}; "
+          f"rel L2 dm0 {e[0]:.2e} dh {e[1]:.2e} dMs {e[2]:.2e}")
+    assert abs(loss - lo) < 1e-5 * lo
+    assert max(e) < 5e-5
+
+
+def test_workload_geometry_T100_vs_stored_oracle(gpu_lib):
+    """The 128x128x4 gradient workload (maps, target, material) at
+    dt = 2e-14 over T = 100 steps (10-step segments): loss and gradients at
+    4096 stored cells against the oracle's FP64 adjoint, written by
+    tests/golden/make_adjoint_film128.py."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "adjoint_film128x128x4_T100.npz"))
+    w = workloads.FILM_128x128x4
+    m0, ms, h, t = workloads.adjoint_inputs(w)
+    T, dt = int(ref["T"]), float(ref["dt"])
+    loss, gm, gh, gms, _ = gpu_grads(gpu_lib, w, m0, ms, h, t, T, dt)
+    c = ref["cells"]
+    e = (rel(gm.reshape(3, -1)[:, c], ref["gm"]), rel(gh.reshape(3, -1)[:, c], ref["gh"]),
+         rel(gms.reshape(-1)[c], ref["gms"]))
+    norms = np.array([np.linalg.norm(gm), np.linalg.norm(gh), np.linalg.norm(gms)])
+    print(f"adjoint 128x128x4 T={T} dt={dt}: loss {loss:.9e} vs {float(ref['loss']):.9e}; rel L2 at "
+          f"{c.size} cells dm0 {e[0]:.2e} dh {e[1]:.2e} dMs {e[2]:.2e}; norms ratio {norms / ref['norms']}")
+    assert abs(loss - float(ref["loss"])) < 1e-6 * float(ref["loss"])
+    assert max(e) < 5e-6
+    assert np.abs(norms / ref["norms"] - 1).max() < 5e-6

@@ -1,11 +1,14 @@
 """Batched samples on the GPU: grouped launches per padded size, one shared
 tensor spectrum per padded size, hipGraph-captured step chunks.
 
-Checks: graph replays equal eager batched steps bit for bit; every member
-after 100 steps within 1e-5 relative L2 of its own single-sample run (the
-members use the group's spectrum, built for the group's largest extent, so
-the FP32 spectra differ in rounding only); the two smallest members within
-1e-4 of the FP64 oracle after 100 steps.
+Workload: the 64 films of the batched workload (sizes drawn between
+64x64x1 and 256x128x2 cells of 4x4x3 nm, each with its own field).
+Checks: graph replays equal eager batched steps bit for bit; every one of
+the 64 members after 100 steps within 1e-6 relative L2 of its own
+single-sample run (the members use the group's spectrum, built for the
+group's largest extent, so the FP32 spectra differ in rounding only); the
+four smallest members within 1e-4 relative L2 (1e-3 per cell) of the FP64
+oracle after 100 steps.
 
 Paper: Zhu, arXiv:1411.2565, Sec. 3 (FFT demag, exchange, Euler) applied to
 each sample independently.
@@ -23,13 +26,18 @@ def rel(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b))
 
 
+def cellmax(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / np.abs(b).max()
+
+
 def host(t):
     return t.detach().cpu().double().numpy()
 
 
 @pytest.fixture(scope="module")
 def films():
-    return workloads.batch_films(count=12, seed=0)
+    return workloads.batch_films(count=64, seed=0)
 
 
 def test_batch_members_match_single_runs(gpu_lib, films):
@@ -41,17 +49,17 @@ def test_batch_members_match_single_runs(gpu_lib, films):
     m = B.pack([m0 for (_, m0, _) in films])
     B.step(m, 100, w0.dt)
     B.sync()
-    groups = {}
+    worst = 0.0
     for i, (w, m0, h) in enumerate(films):
         sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=tuple(h))
         ms = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
         sim.step(ms, 100, w.dt)
         sim.sync()
         e = rel(host(B.unpack(m, i)), host(ms))
-        groups.setdefault(tuple(B.unpack(m, i).shape), []).append(e)
-        print(f"member {i} {w.n}: rel L2 vs single run {e:.2e}")
-        assert e < 1e-5
+        worst = max(worst, e)
+        assert e < 1e-6, (i, w.n, e)
         sim.close()
+    print(f"64 members vs their single runs after 100 steps: worst rel L2 {worst:.2e}")
     B.close()
 
 
@@ -83,14 +91,14 @@ def test_batch_smallest_members_vs_oracle(gpu_lib, films):
     m_in = [host(B.unpack(m, i)) for i in range(len(films))]
     B.step(m, 100, w0.dt)
     B.sync()
-    order = np.argsort([w.N for (w, _, _) in films])[:2]
+    order = np.argsort([w.N for (w, _, _) in films])[:4]
     for i in order:
         w, _, h = films[i]
         P = oracle.Problem(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=h)
         mo = P.run(m_in[i], 100, w.dt)
-        e = rel(host(B.unpack(m, i)), mo)
-        print(f"member {i} {w.n} vs oracle, 100 steps: rel L2 {e:.2e}")
-        assert e < 1e-4
+        e, c = rel(host(B.unpack(m, i)), mo), cellmax(host(B.unpack(m, i)), mo)
+        print(f"member {i} {w.n} vs oracle, 100 steps: rel L2 {e:.2e}, cell max {c:.2e}")
+        assert e < 1e-4 and c < 1e-3
     B.close()
 
 
