@@ -480,6 +480,8 @@ def main():
     ap.add_argument("--settle-steps", type=int, default=300,
                     help="untimed steps before the warm-up: the GPU ramps its clocks over the first "
                          "~100-300 steps of a burst")
+    ap.add_argument("--profile-steps", type=int, default=200,
+                    help="steps of the per-kernel event-timed region that follows the timed region")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--compensated", action="store_true",
                     help="run the headline timing with the compensated spectral multiply")
@@ -489,6 +491,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
     ap.add_argument("--sweep", action="store_true",
                     help="also time the N^3 cube size sweep and the standard problem #4 film")
+    ap.add_argument("--sweep-sizes", type=int, nargs="+", default=None,
+                    help="with --sweep: only these cube sizes N, and no standard problem #4 film")
     ap.add_argument("--integrators", action="store_true",
                     help="also time the Heun, RK4 and adaptive steps on the block")
     ap.add_argument("--geometry", action="store_true",
@@ -524,20 +528,26 @@ def main():
     sim.step(m, args.warmup, w.dt, flags)
     sim.sync()
 
-    # the timed region; every kernel's dispatch records its own start and
-    # stop events on the launch stream (per-kernel durations of this region)
     print(f"bench: timing {args.steps} steps", file=sys.stderr, flush=True)
-    binding.mm_kernel_timing(sim.ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(m, args.steps, w.dt, flags)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    times = binding.mm_kernel_times(sim.ctx)
-    binding.mm_kernel_timing(sim.ctx, False)
     sim.sync()
     ms_step = 1e3 * el / max(args.steps, 1)
     value = w.N * args.steps / el
+
+    # per-kernel durations: right after the timed region, the same steps
+    # again with every kernel's dispatch recording its own start and stop
+    # events on the launch stream.  (Recording them inside the timed region
+    # itself was measured to add about 15 us of gaps per step.)
+    print(f"bench: per-kernel event timing over {args.profile_steps} steps", file=sys.stderr, flush=True)
+    binding.mm_kernel_timing(sim.ctx, True)
+    sim.step(m, args.profile_steps, w.dt, flags)
+    times = binding.mm_kernel_times(sim.ctx)
+    binding.mm_kernel_timing(sim.ctx, False)
+    sim.sync()
     P = tuple(padded(v) for v in w.n)
     kb = kernel_bytes(w.n, P)
     kernels = {}
@@ -569,9 +579,10 @@ def main():
     sweep = sp4 = None
     if args.sweep:
         print("bench: N^3 cube size sweep", file=sys.stderr, flush=True)
-        sweep = size_sweep(binding)
-        print("bench: standard problem #4 film", file=sys.stderr, flush=True)
-        sp4 = sp4_rate(binding)
+        sweep = size_sweep(binding, args.sweep_sizes)
+        if not args.sweep_sizes:
+            print("bench: standard problem #4 film", file=sys.stderr, flush=True)
+            sp4 = sp4_rate(binding)
 
     rk = None
     if args.integrators:
@@ -602,6 +613,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "settle_steps": args.settle_steps,
+        "profile_steps": args.profile_steps,
         "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",

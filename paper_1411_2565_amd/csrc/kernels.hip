@@ -136,6 +136,11 @@ struct ZShape {
     static constexpr int CBmax = cmax(1, (KB * 1024) / (3 * 8 * lds_line(L)));
     static constexpr int CB0 = cmin(cmin(cmax(1, 1024 / T), pow2floor(CBmax)), L >= 128 ? MMK_ZC_CB_LONG : 1024);
     static constexpr int CB = V == 2 ? cmax(1, CB0 / 2) : CB0;
+    // Long transforms whose LDS budget leaves fewer than 16 columns per
+    // pass: one block takes NSUB adjacent tiles of CB columns in turn, so the
+    // 128-byte rows of S2 that the tiles share are read by one block, back
+    // to back, instead of by blocks on different XCDs.
+    static constexpr int NSUB = (L >= 128 && CB < 16) ? 16 / CB : 1;
     static constexpr int THREADS = T * CB;
     static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
 };
@@ -414,73 +419,80 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, 
     const Geo &g = D.g;
     float2 *__restrict__ S2 = D.S2;
     const float *__restrict__ K = D.K;
+    constexpr int NSUB = S::NSUB;
     const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
     const int kx = blockIdx.y;
-    const int tile = zc_tile(blockIdx.x, gridDim.x);
+    const int stile = zc_tile(blockIdx.x, gridDim.x);
     // a batch launch covers the largest sample: whole tiles beyond this one
     // leave (block-uniform, before any barrier)
-    if (kx >= g.Hx || tile * CB >= g.Py) return;
-    const int ky = tile * CB + col;
-    const bool ok = ky < g.Py;
-    const long long zs = g.Py;                                // stride between z
-    const long long cs = (long long)g.Hx * g.nz * g.Py;       // between components
-    float2 *base = S2 + (long long)kx * g.nz * g.Py + ky;
-    float2 v[3][E];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int zz = t + q * T;
-            v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[c * cs + zz * zs]
-                                                           : make_float2(0.f, 0.f);
-        }
-    // one twiddle set for both transforms, loaded while the data arrive
-    TwSet<L, E> tw;
-    load_twiddles<L, E>(tw, t);
-    const int hy = g.Py / 2, hz = g.Pz / 2;
-    const bool fy = ky > hy;
-    const int kyf = fy ? g.Py - ky : ky;
-    const float sy = fy ? -1.f : 1.f;
-    // this column's octant entries: K[kx][kyf][kz][6], contiguous over kz
-    const float *kcol = K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
-    float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
-                            sm + (2 * CB + col) * lds_line(L)};
-    reg_fft<L, false>(v, lds, t, tw);
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int kz = t + q * T;
-        const bool fz = kz > hz;
-        const int kzf = fz ? g.Pz - kz : kz;
-        const float sz = fz ? -1.f : 1.f;
-        float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
-        if (ok) {
-            const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
-            k01 = kp[0];
-            k23 = kp[1];
-            k45 = kp[2];
-        }
-        const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
-        const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
-        const float2 mx = v[0][q], my = v[1][q], mz = v[2][q];
-        if (COMP) {
-            v[0][q] = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
-            v[1][q] = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
-            v[2][q] = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
-        } else {
-            v[0][q] = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
-            v[1][q] = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
-            v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
-        }
-    }
-    reg_fft<L, true>(v, lds, t, tw);
-    if (ok) {
+    if (kx >= g.Hx || stile * NSUB * CB >= g.Py) return;
+    // every exchange of an FFT ends with a block barrier after its LDS
+    // reads, so the next tile's first LDS writes cannot overtake them
+    for (int sub = 0; sub < NSUB; ++sub) {
+        const int tile = stile * NSUB + sub;
+        if (tile * CB >= g.Py) break;  // block-uniform
+        const int ky = tile * CB + col;
+        const bool ok = ky < g.Py;
+        const long long zs = g.Py;                                // stride between z
+        const long long cs = (long long)g.Hx * g.nz * g.Py;       // between components
+        float2 *base = S2 + (long long)kx * g.nz * g.Py + ky;
+        float2 v[3][E];
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int q = 0; q < half_elems(E); ++q) {
+            for (int q = 0; q < E; ++q) {
                 const int zz = t + q * T;
-                if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
+                v[c][q] = (q < half_elems(E) && ok && zz < g.nz) ? base[c * cs + zz * zs]
+                                                               : make_float2(0.f, 0.f);
             }
+        // one twiddle set for both transforms, loaded while the data arrive
+        TwSet<L, E> tw;
+        load_twiddles<L, E>(tw, t);
+        const int hy = g.Py / 2, hz = g.Pz / 2;
+        const bool fy = ky > hy;
+        const int kyf = fy ? g.Py - ky : ky;
+        const float sy = fy ? -1.f : 1.f;
+        // this column's octant entries: K[kx][kyf][kz][6], contiguous over kz
+        const float *kcol = K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
+        float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
+                                sm + (2 * CB + col) * lds_line(L)};
+        reg_fft<L, false>(v, lds, t, tw);
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int kz = t + q * T;
+            const bool fz = kz > hz;
+            const int kzf = fz ? g.Pz - kz : kz;
+            const float sz = fz ? -1.f : 1.f;
+            float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
+            if (ok) {
+                const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
+                k01 = kp[0];
+                k23 = kp[1];
+                k45 = kp[2];
+            }
+            const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
+            const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
+            const float2 mx = v[0][q], my = v[1][q], mz = v[2][q];
+            if (COMP) {
+                v[0][q] = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
+                v[1][q] = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
+                v[2][q] = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
+            } else {
+                v[0][q] = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
+                v[1][q] = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
+                v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
+            }
+        }
+        reg_fft<L, true>(v, lds, t, tw);
+        if (ok) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int q = 0; q < half_elems(E); ++q) {
+                    const int zz = t + q * T;
+                    if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
+                }
+        }
     }
 }
 
@@ -1585,7 +1597,8 @@ hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s, int
         with_variant<LL>(comp ? 0 : var, count, [&](auto vt) {                                \
             constexpr int VV = decltype(vt)::value;                                           \
             using S = ZShape<LL, VV>;                                                         \
-            dim3 grid((e.Py + S::CB - 1) / S::CB, e.Hx, count);                               \
+            constexpr int CT = S::CB * S::NSUB;                                               \
+            dim3 grid((e.Py + CT - 1) / CT, e.Hx, count);                                     \
             const size_t lds = S::LDS * sizeof(float2);                                       \
             if (comp) {                                                                       \
                 if constexpr (VV == 0) MM_PASS_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, 0, LL, true); \
