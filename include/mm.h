@@ -220,6 +220,19 @@ mm_status mm_reduce(mm_ctx *c, const float *m_dev, double *out_dev);
 mm_status mm_reduce_loss(mm_ctx *c, const float *m_dev, const float *target_dev, double *out_dev,
                          float *grad_dev);
 
+/* The same loss for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * identical arguments and results as mm_reduce_loss, bit for bit (the same
+ * kernels), but the partial sums live in a static array of the library
+ * (4096 FP64 values, 32 KiB, held on every GPU the library runs on until the
+ * process ends) instead of the workspace.  Needs no workspace; allocates
+ * nothing and calls no allocating routine.  Contexts of more than
+ * 2 796 202 cells (N with 3N > 4096 * 2048) return MM_EINVAL.  Every call on
+ * one GPU shares that array: calls that may overlap on one GPU (several
+ * streams or threads) race and must be serialised by the caller. */
+mm_status mm_reduce_loss_noalloc(mm_ctx *c, const float *m_dev, const float *target_dev, double *out_dev,
+                                 float *grad_dev);
+
 /* Use (on != 0) or stop using the compensated FP32 spectral multiply in every
  * demag evaluation of this context (mm_compute_heff, mm_reduce, steps and
  * adjoint steps), in addition to per-call MM_F_COMPENSATED. */

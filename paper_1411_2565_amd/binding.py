@@ -82,6 +82,7 @@ def load():
         "mm_set_time": [_P, ctypes.c_double],
         "mm_get_time": [_P, ctypes.POINTER(ctypes.c_double)],
         "mm_reduce_loss": [_P, _P, _P, _P, _P],
+        "mm_reduce_loss_noalloc": [_P, _P, _P, _P, _P],
     }
     sig.update({
         "mm_batch_create": [ctypes.POINTER(_P), ctypes.c_int, ctypes.POINTER(ctypes.c_int32), ctypes.c_double,
@@ -218,6 +219,14 @@ def mm_reduce_loss(ctx, m, target, out, grad, N):
     _check(ctx, load().mm_reduce_loss(ctx, _dev(m, torch.float32, 3 * N, "m"),
                                       _dev(target, torch.float32, 3 * N, "target"),
                                       _dev(out, torch.float64, 1, "out"), g), "mm_reduce_loss")
+
+
+def mm_reduce_loss_noalloc(ctx, m, target, out, grad, N):
+    import torch
+    g = None if grad is None else _dev(grad, torch.float32, 3 * N, "grad")
+    _check(ctx, load().mm_reduce_loss_noalloc(ctx, _dev(m, torch.float32, 3 * N, "m"),
+                                              _dev(target, torch.float32, 3 * N, "target"),
+                                              _dev(out, torch.float64, 1, "out"), g), "mm_reduce_loss_noalloc")
 
 
 def mm_set_field_schedule(ctx, sched):

@@ -140,6 +140,9 @@ bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 std::mutex g_init_mu;
 bool g_init_done[64] = {false};
+// per device: address of the library's static scratch array (see
+// mm_reduce_loss_noalloc), looked up once with that device current
+double *g_scratch[64] = {nullptr};
 
 // device tables (twiddles) once per device, with that device current
 mm_status init_device(mm_ctx *c)
@@ -147,8 +150,11 @@ mm_status init_device(mm_ctx *c)
     std::lock_guard<std::mutex> lk(g_init_mu);
     if (c->device < 0 || c->device >= 64) return fail(c, MM_EINVAL, "device index %d out of range", c->device);
     if (g_init_done[c->device]) return MM_OK;
-    MM_TRY(hipcheck(c, mmk::init_tables(c->stream), "init_tables"));
+    double *sc = nullptr;
+    MM_TRY(hipcheck(c, mmk::init_tables(c->stream, &sc), "init_tables"));
     MM_TRY(hipcheck(c, hipStreamSynchronize(c->stream), "init_tables sync"));
+    if (!sc) return fail(c, MM_EHIP, "no device address for the static scratch");
+    g_scratch[c->device] = sc;
     g_init_done[c->device] = true;
     return MM_OK;
 }
@@ -1051,6 +1057,27 @@ mm_status mm_reduce_loss(mm_ctx *c, const float *m, const float *target, double 
     MM_TRY(set_device(c));
     return hipcheck(c, mmk::launch_loss(m, target, 3 * c->g.N, grad, c->at<double>(c->o_lpart), out, c->stream),
                     "loss");
+}
+
+mm_status mm_reduce_loss_noalloc(mm_ctx *c, const float *m, const float *target, double *out, float *grad)
+{
+    if (!c) return MM_EINVAL;
+    if (!m || !target || !out || !aligned16(m) || !aligned16(target) || !aligned16(out))
+        return fail(c, MM_EINVAL, "m, target and out must be 16-byte aligned device pointers");
+    if (grad && !aligned16(grad)) return fail(c, MM_EINVAL, "grad must be 16-byte aligned");
+    if (grad && (grad == m || grad == target)) return fail(c, MM_EINVAL, "grad may not alias m or target");
+    const long long n = 3 * c->g.N;
+    if (mmk::loss_partials(n) > mmk::kScratchPartials)
+        return fail(c, MM_EINVAL, "%lld cells exceed the static scratch of the no-allocation loss (at most %lld cells)",
+                    (long long)c->g.N, mmk::kScratchPartials * mmk::kLossChunk / 3);
+    double *sc = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_init_mu);
+        sc = g_scratch[c->device];
+    }
+    if (!sc) return fail(c, MM_ESTATE, "device %d has no static scratch address", c->device);
+    MM_TRY(set_device(c));
+    return hipcheck(c, mmk::launch_loss(m, target, n, grad, sc, out, c->stream), "loss (static scratch)");
 }
 
 mm_status mm_kernel_timing(mm_ctx *c, int enable)

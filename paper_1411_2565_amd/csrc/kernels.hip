@@ -36,8 +36,21 @@ __global__ void k_init_tw()
     }
 }
 
-hipError_t init_tables(hipStream_t s)
+// Scratch of the loss reduction for callers that cannot allocate
+// (mm_reduce_loss_noalloc): FP64 partial sums, one per block of the
+// reduction.  A __device__ array, so each GPU the library runs on holds its
+// own copy, at its own address, until the process ends.  Host code never
+// passes this name to a kernel: it uses the address init_tables looks up.
+static __device__ __align__(256) double scratch[kScratchPartials];
+
+// Per device, with that device current: the twiddle table, and the device
+// address of `scratch` into *scratch_dev.
+hipError_t init_tables(hipStream_t s, double **scratch_dev)
 {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    *scratch_dev = static_cast<double *>(p);
     hipLaunchKernelGGL(k_init_tw, dim3(MAXL / 256), dim3(256), 0, s);
     return hipGetLastError();
 }

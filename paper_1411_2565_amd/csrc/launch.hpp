@@ -106,7 +106,13 @@ struct EnergyParams {
 
 constexpr int kEnergyBlocks = 512;
 
-hipError_t init_tables(hipStream_t s);
+// Partial sums the static scratch of the loss reduction holds: up to
+// kScratchPartials * kLossChunk values (2 796 202 cells of 3 components).
+constexpr long long kScratchPartials = 4096;
+
+// once per device, with that device current: device tables, and the
+// address of the static scratch array on this device
+hipError_t init_tables(hipStream_t s, double **scratch_dev);
 
 // demag pipeline, batched: `count` (1..kMaxBatch) samples sharing Px, Py, Pz
 // Pass launchers.  `var` selects a launch-shape variant (0 = default, 1, 2;
