@@ -212,9 +212,11 @@ def adjoint_ratio(binding, T=2000):
 
 
 def batch_rate(binding, steps=5000, single_steps=200):
-    """Aggregate cell-steps/s of the 64-film batch (grouped launches per
-    padded size, 32-step hipGraph chunks) against the same films stepped one
-    by one (eager launches), on the same GPU."""
+    """Aggregate cell-steps/s of the 64-film batch (one launch per pass and
+    transform length, 32-step hipGraph chunks), then with the launch shapes
+    the batch autotuner picks, against the same films stepped one by one
+    (eager launches, and each film replaying its own graphs), on the same
+    GPU."""
     import torch
     from paper_1411_2565_amd import workloads
     films = workloads.batch_films(count=64, seed=0)
@@ -232,6 +234,15 @@ def batch_rate(binding, steps=5000, single_steps=200):
         B.step(m, steps, w0.dt, binding.MM_F_GRAPH)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        # the same batch with launch shapes chosen by the batch autotuner
+        choice = B.autotune(None)
+        B.step(m, 64, w0.dt, binding.MM_F_GRAPH)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.step(m, steps, w0.dt, binding.MM_F_GRAPH)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        launches = len(choice)
         B.sync()
         B.close()
         sims = []
@@ -260,6 +271,8 @@ def batch_rate(binding, steps=5000, single_steps=200):
             sim.close()
     return {"workload": f"64 films, {cells} cells in all, 4x4x3 nm, dt=5e-14",
             "batched_cell_steps_per_s": cells * steps / tb, "batched_us_per_step": round(1e6 * tb / steps, 1),
+            "tuned_us_per_step": round(1e6 * tt / steps, 1), "tuned_choice_xyz_launches": list(choice),
+            "tunable_launches": launches,
             "one_by_one_cell_steps_per_s": cells * single_steps / ts,
             "one_by_one_us_per_step": round(1e6 * ts / single_steps, 1),
             "one_by_one_graph_us_per_step": round(1e6 * tsg / single_steps, 1),

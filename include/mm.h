@@ -335,8 +335,13 @@ mm_status mm_kernel_times(mm_ctx *c, double *ms, int64_t *launches);
 /* ---- Batched samples --------------------------------------------------
  * Many independent grids of rectangular cells (one cell size and material,
  * each its own nx, ny, nz and uniform external field) advanced together by
- * the same step as mm_step_llg.  Samples with equal padded sizes share one
- * tensor spectrum and one launch per pass (up to 64 samples per launch).
+ * the same step as mm_step_llg (Sec. 3, applied to each sample).  Samples
+ * with equal padded sizes share one tensor spectrum.  Each pass runs as one
+ * launch per transform length (x by Px, y by Py, z by Pz; the local update
+ * by whether nx is a multiple of 4) over all samples of that length; the
+ * per-sample descriptors of every launch live in the workspace and are
+ * written (synchronously) by the first mm_batch_step for a state pointer
+ * and after a setter.
  * The state of all samples is one packed FP32 device array: sample b's
  * [3][nz][ny][nx] block starts at float offset offsets[b]
  * (mm_batch_state_offsets), each block 16-byte aligned. */
@@ -362,6 +367,23 @@ mm_status mm_batch_build_tensor(mm_batch *b);
 /* nsteps Euler steps of every sample, in place in the packed state; flags
  * as mm_step_llg (MM_F_GRAPH captures chunks of 32 steps of the whole batch) */
 mm_status mm_batch_step(mm_batch *b, float *m_packed, int64_t nsteps, double dt, uint32_t flags);
+/* Launch-shape tuning of the batch's launches (the paper leaves FFT
+ * performance to its FFT library, Sec. 3): one choice in
+ * [0, MM_TUNE_VARIANTS) per x, y and z launch, in that order and, within a
+ * pass, by increasing transform length; *n receives their number.  The
+ * variants are those of mm_set_tuning (x and y regroup lines: results equal
+ * the default bit for bit; z changes the radix split: rounding only) and
+ * apply to launches whose lines have 64 points or more (others keep 0).
+ * mm_batch_autotune times every variant of every launch (2 + 10 runs on
+ * zeroed sample buffers, HIP events on the batch's stream, synchronous),
+ * keeps the fastest and appends it to cache_path (if not NULL) under the
+ * GPU's arch name and a hash of the sample sizes; a matching line already in
+ * the file is taken without timing.  choices (capacity entries, may be NULL)
+ * receives the result.  Needs the workspace, material and tensor; overwrites
+ * the samples' FFT buffers and temporaries, not the caller's state. */
+mm_status mm_batch_autotune(mm_batch *b, const char *cache_path, int32_t *choices, int32_t capacity, int32_t *n);
+mm_status mm_batch_set_tuning(mm_batch *b, const int32_t *choices, int32_t n);
+mm_status mm_batch_get_tuning(const mm_batch *b, int32_t *choices, int32_t capacity, int32_t *n);
 mm_status mm_batch_sync(mm_batch *b);
 const char *mm_batch_last_error(const mm_batch *b);
 

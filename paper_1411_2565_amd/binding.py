@@ -97,6 +97,10 @@ def load():
         "mm_batch_build_tensor": [_P],
         "mm_batch_step": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32],
         "mm_batch_sync": [_P],
+        "mm_batch_autotune": [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_int32)],
+        "mm_batch_set_tuning": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
+        "mm_batch_get_tuning": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     })
     for name, args in sig.items():
         f = getattr(L, name)
@@ -384,6 +388,29 @@ def mm_batch_sync(b):
     _bcheck(b, load().mm_batch_sync(b), "mm_batch_sync")
 
 
+def mm_batch_get_tuning(b):
+    n = ctypes.c_int32()
+    _bcheck(b, load().mm_batch_get_tuning(b, None, 0, ctypes.byref(n)), "mm_batch_get_tuning")
+    arr = (ctypes.c_int32 * max(n.value, 1))()
+    _bcheck(b, load().mm_batch_get_tuning(b, arr, n.value, ctypes.byref(n)), "mm_batch_get_tuning")
+    return tuple(arr[:n.value])
+
+
+def mm_batch_set_tuning(b, choices):
+    arr = (ctypes.c_int32 * max(len(choices), 1))(*[int(v) for v in choices])
+    _bcheck(b, load().mm_batch_set_tuning(b, arr, len(choices)), "mm_batch_set_tuning")
+
+
+def mm_batch_autotune(b, cache_path=None):
+    """Fastest launch-shape variant of each x, y and z launch of the batch."""
+    n = len(mm_batch_get_tuning(b))
+    arr = (ctypes.c_int32 * max(n, 1))()
+    cnt = ctypes.c_int32()
+    path = None if cache_path is None else os.fsencode(cache_path)
+    _bcheck(b, load().mm_batch_autotune(b, path, arr, n, ctypes.byref(cnt)), "mm_batch_autotune")
+    return tuple(arr[:cnt.value])
+
+
 class Batch:
     """Many independent samples (own sizes and uniform fields, one cell size
     and material) on one GPU; the state is one packed tensor."""
@@ -425,6 +452,16 @@ class Batch:
         mm_batch_set_stream(self.b)
         mm_batch_step(self.b, m, nsteps, dt, flags, self.total)
         return m
+
+    def autotune(self, cache_path=None):
+        mm_batch_set_stream(self.b)
+        return mm_batch_autotune(self.b, cache_path)
+
+    def set_tuning(self, choices):
+        mm_batch_set_tuning(self.b, choices)
+
+    def tuning(self):
+        return mm_batch_get_tuning(self.b)
 
     def sync(self):
         mm_batch_sync(self.b)

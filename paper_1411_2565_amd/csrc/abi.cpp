@@ -1133,12 +1133,24 @@ const char *mm_last_error(const mm_ctx *c)
 
 // ===========================================================================
 // Batched samples: many independent grids (each its own nx, ny, nz and
-// external field, one cell size and material) advanced together.  Samples
-// with the same padded size form a group; every pass runs as one launch per
-// group of up to kMaxBatch samples.  The tensor spectrum depends only on the
-// padded size and the cell size, so each group shares one spectrum, built as
-// for an (Px/2, Py/2, Pz/2) grid: a sample with n <= P/2 never reaches the
-// offsets beyond its own extent in the zero-padded convolution.
+// external field, one cell size and material) advanced together.  The tensor
+// spectrum depends only on the padded size and the cell size, so samples of
+// one padded size share one spectrum, built as for an (Px/2, Py/2, Pz/2)
+// grid: a sample with n <= P/2 never reaches the offsets beyond its own
+// extent in the zero-padded convolution.
+//
+// Launch plan: each pass depends only on its own transform length, so the
+// samples are grouped per pass by that length alone (x by Px, y by Py, z by
+// Pz; the local kernel by whether nx is a multiple of 4, its vector width),
+// and each group runs as one launch.  The per-sample descriptors live in the
+// workspace, so a launch carries one pointer; its grid is (blocks, samples),
+// as wide as the group's largest sample, rounded up to a multiple of 8 so
+// that every sample keeps the XCD placement of a single-sample launch.
+// (A one-dimensional grid holding exactly the samples' blocks, found through
+// a block-to-sample map in device memory, was measured slower on the
+// 64-film batch, 187 against 180 us per step: the map read puts a second
+// dependent memory access before each block's first load, which costs more
+// than the blocks beyond a smaller sample's grid, which exit after one.)
 // ===========================================================================
 
 struct mm_batch {
@@ -1159,11 +1171,23 @@ struct mm_batch {
         size_t o_K = 0;      // its tensor spectrum
         std::vector<int> members;
     };
+    // one launch of a pass: samples with one transform length
+    struct Launch {
+        int pass = 0;                   // 0 x, 1 y, 2 z, 3 local
+        int len = 0;                    // Px, Py, Pz; local: 1 if nx % 4 == 0
+        int var = 0;                    // launch-shape variant
+        std::vector<int> members;
+        long long width = 0;            // blocks per sample in the grid (current variant)
+        size_t o_desc[3] = {0, 0, 0};   // descriptor arrays (see plan_image)
+    };
     std::vector<Sample> samples;
     std::vector<Group> groups;
+    std::vector<Launch> launches;       // x, then y, then z, then local
     size_t total_state = 0;  // floats in the packed state
-    size_t o_flag = 0, total = 0;
+    size_t o_flag = 0, o_plan = 0, plan_bytes = 0, total = 0;
     char *ws = nullptr;
+    const float *plan_m = nullptr;  // state pointer the uploaded descriptors were written for
+    bool plan_ok = false;
     std::string err;
     std::vector<hipGraphExec_t> graph_exec;
     std::vector<std::pair<const float *, std::pair<int64_t, double>>> graph_key;
@@ -1237,122 +1261,208 @@ mmk::LocalParams batch_params(const mm_batch *b)
     return p;
 }
 
-// enqueue nsteps steps of every sample (no checks)
-// Launch lists of one batched step: each pass depends only on its own
-// transform length (x on Px, y on Py, z on Pz), so samples are grouped per
-// pass by that length alone, in chunks of up to kMaxBatch, rather than by
-// their whole padded size; the local pass takes any mix (chunks split by
-// whether nx is a multiple of 4, for its vector width).
-struct BatchPlan {
-    std::vector<std::vector<int>> x, y, z, loc;
-    std::vector<const float *> K;  // tensor spectrum of each sample's padded size
-};
+const float *spectrum_of(const mm_batch *b, int i) { return b->at<float>(b->groups[b->samples[i].group].o_K); }
 
-BatchPlan batch_plan(mm_batch *b)
+// blocks of sample i's own grid in launch L with variant v, and the padded
+// count that launch gives it.  A z launch with the compensated multiply runs
+// variant 0 whatever its tuned variant, so its map covers the larger of the
+// two grids (the kernel's bounds check retires the blocks its own grid does
+// not have).
+long long sample_blocks(const mm_batch *b, const mm_batch::Launch &L, int i, int v)
 {
-    BatchPlan pl;
-    const int ns = (int)b->samples.size();
-    pl.K.assign(ns, nullptr);
-    for (const auto &gr : b->groups)
-        for (int i : gr.members) pl.K[i] = b->at<float>(gr.o_K);
-    auto split = [&](auto key, std::vector<std::vector<int>> &out) {
-        std::vector<std::pair<long long, int>> keyed;
-        for (int i = 0; i < ns; ++i) keyed.push_back({key(b->samples[i].g), i});
-        std::stable_sort(keyed.begin(), keyed.end(),
-                         [](const auto &u, const auto &v) { return u.first < v.first; });
-        for (size_t k = 0; k < keyed.size();) {
-            std::vector<int> chunk;
-            const long long kk = keyed[k].first;
-            while (k < keyed.size() && keyed[k].first == kk && (int)chunk.size() < mmk::kMaxBatch)
-                chunk.push_back(keyed[k++].second);
-            out.push_back(chunk);
-        }
-    };
-    split([](const mmk::Geo &g) { return (long long)g.Px; }, pl.x);
-    split([](const mmk::Geo &g) { return (long long)g.Py; }, pl.y);
-    split([](const mmk::Geo &g) { return (long long)g.Pz; }, pl.z);
-    split([](const mmk::Geo &g) { return (long long)(g.nx % 4 == 0); }, pl.loc);
-    return pl;
+    const mmk::Geo &g = b->samples[i].g;
+    if (L.pass == 3) return mmk::local_blocks(g, L.len != 0);
+    if (L.pass == 2) return std::max(mmk::pass_blocks(2, g, v), mmk::pass_blocks(2, g, 0));
+    return mmk::pass_blocks(L.pass, g, v);
+}
+long long launch_width(const mm_batch *b, const mm_batch::Launch &L, int v)
+{
+    long long n = 0;
+    for (int i : L.members) n = std::max(n, sample_blocks(b, L, i, v));
+    return (n + 7) & ~7LL;
 }
 
-mm_status batch_enqueue(mm_batch *b, float *m, int64_t nsteps, double dt, uint32_t flags)
+// group the samples into launches (at creation: depends on the sizes only)
+void plan_launches(mm_batch *b)
+{
+    b->launches.clear();
+    const int ns = (int)b->samples.size();
+    for (int pass = 0; pass < 4; ++pass) {
+        std::vector<std::pair<int, int>> keyed;
+        for (int i = 0; i < ns; ++i) {
+            const mmk::Geo &g = b->samples[i].g;
+            const int key = pass == 0 ? g.Px : pass == 1 ? g.Py : pass == 2 ? g.Pz : (g.nx % 4 == 0 ? 1 : 0);
+            keyed.push_back({key, i});
+        }
+        std::stable_sort(keyed.begin(), keyed.end(), [](const auto &u, const auto &v) { return u.first < v.first; });
+        for (size_t k = 0; k < keyed.size();) {
+            mm_batch::Launch L;
+            L.pass = pass;
+            L.len = keyed[k].first;
+            while (k < keyed.size() && keyed[k].first == L.len) L.members.push_back(keyed[k++].second);
+            b->launches.push_back(L);
+        }
+    }
+    for (auto &L : b->launches) L.width = launch_width(b, L, 0);
+}
+
+// workspace bytes of the plan region, and the offsets of every array in it
+size_t plan_layout(mm_batch *b, size_t base)
+{
+    Carve cv;
+    cv.off = base;
+    for (auto &L : b->launches) {
+        const size_t n = L.members.size();
+        switch (L.pass) {
+        case 0:  // xfwd for even steps (reads m), for odd steps (reads the temporary), xinv
+            L.o_desc[0] = cv.take(sizeof(mmk::XfwdDesc) * n);
+            L.o_desc[1] = cv.take(sizeof(mmk::XfwdDesc) * n);
+            L.o_desc[2] = cv.take(sizeof(mmk::XinvDesc) * n);
+            break;
+        case 1:  // forward S1 -> S2, inverse S2 -> S1
+            L.o_desc[0] = cv.take(sizeof(mmk::YDesc) * n);
+            L.o_desc[1] = cv.take(sizeof(mmk::YDesc) * n);
+            break;
+        case 2:
+            L.o_desc[0] = cv.take(sizeof(mmk::ZDesc) * n);
+            break;
+        default:  // local, even and odd steps
+            L.o_desc[0] = cv.take(sizeof(mmk::LocalDesc) * n);
+            L.o_desc[1] = cv.take(sizeof(mmk::LocalDesc) * n);
+        }
+    }
+    return cv.off - base;
+}
+
+// Host image of the plan region for state pointer m: every launch's
+// descriptors.  Even steps read m and write the sample's temporary, odd
+// steps the reverse.
+std::vector<char> plan_image(const mm_batch *b, const float *m)
+{
+    std::vector<char> img(b->plan_bytes, 0);
+    auto put = [&](size_t off, const void *src, size_t bytes) { std::memcpy(img.data() + (off - b->o_plan), src, bytes); };
+    for (const auto &L : b->launches) {
+        for (int par = 0; par < 2; ++par) {
+            for (int k = 0; k < (int)L.members.size(); ++k) {
+                const auto &sm = b->samples[L.members[k]];
+                const float *src = par ? b->at<float>(sm.o_mt) : m + sm.m_off;
+                float *dst = par ? const_cast<float *>(m) + sm.m_off : b->at<float>(sm.o_mt);
+                if (L.pass == 0) {
+                    const mmk::XfwdDesc xf{sm.g, src, nullptr, b->at<float2>(sm.o_S1), (float)b->mat.Ms};
+                    put(L.o_desc[par] + sizeof(xf) * k, &xf, sizeof(xf));
+                    if (par == 0) {
+                        const mmk::XinvDesc xi{sm.g, b->at<float2>(sm.o_S1), b->at<float>(sm.o_S2)};
+                        put(L.o_desc[2] + sizeof(xi) * k, &xi, sizeof(xi));
+                    }
+                } else if (L.pass == 1) {
+                    const mmk::YDesc yd = par ? mmk::YDesc{sm.g, b->at<float2>(sm.o_S2), b->at<float2>(sm.o_S1)}
+                                              : mmk::YDesc{sm.g, b->at<float2>(sm.o_S1), b->at<float2>(sm.o_S2)};
+                    put(L.o_desc[par] + sizeof(yd) * k, &yd, sizeof(yd));
+                } else if (L.pass == 2) {
+                    if (par == 0) {
+                        const mmk::ZDesc zd{sm.g, b->at<float2>(sm.o_S2), spectrum_of(b, L.members[k])};
+                        put(L.o_desc[0] + sizeof(zd) * k, &zd, sizeof(zd));
+                    }
+                } else {
+                    mmk::LocalDesc ld{sm.g, src, b->at<float>(sm.o_S2), nullptr, nullptr, dst, nullptr,
+                                      (float)sm.h[0], (float)sm.h[1], (float)sm.h[2]};
+                    ld.perm_q = mmk::local_perm(sm.g, L.len != 0);
+                    put(L.o_desc[par] + sizeof(ld) * k, &ld, sizeof(ld));
+                }
+            }
+        }
+    }
+    return img;
+}
+
+// write the plan for state pointer m into the workspace (waits for the
+// stream first: earlier launches may still read the old plan)
+mm_status plan_upload(mm_batch *b, const float *m)
+{
+    if (b->plan_ok && b->plan_m == m) return MM_OK;
+    const std::vector<char> img = plan_image(b, m);
+    MM_TRY(bhip(b, hipStreamSynchronize(b->stream), "plan sync"));
+    MM_TRY(bhip(b, hipMemcpy(b->at<char>(b->o_plan), img.data(), img.size(), hipMemcpyHostToDevice), "plan upload"));
+    b->drop_graphs();
+    b->plan_m = m;
+    b->plan_ok = true;
+    return MM_OK;
+}
+
+template <typename D>
+mmk::Table<D> table_of(const mm_batch *b, const mm_batch::Launch &L, int which)
+{
+    return mmk::Table<D>{b->at<D>(L.o_desc[which]), L.width, (int)L.members.size()};
+}
+
+// enqueue nsteps steps of every sample (plan uploaded for m, no checks)
+mm_status batch_enqueue(mm_batch *b, int64_t nsteps, double dt, uint32_t flags)
 {
     const mmk::LocalParams p = batch_params(b);
     const bool comp = flags & MM_F_COMPENSATED;
     const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
     int *flag = b->at<int>(b->o_flag);
     hipStream_t st = b->stream;
-    const BatchPlan pl = batch_plan(b);
-    std::vector<mmk::XfwdDesc> xf;
-    std::vector<mmk::YDesc> yd;
-    std::vector<mmk::ZDesc> zc;
-    std::vector<mmk::XinvDesc> xi;
-    std::vector<mmk::LocalDesc> lc;
     for (int64_t s = 0; s < nsteps; ++s) {
-        auto src_of = [&](const mm_batch::Sample &sm) -> const float * {
-            return (s & 1) ? b->at<float>(sm.o_mt) : m + sm.m_off;
-        };
-        auto dst_of = [&](const mm_batch::Sample &sm) -> float * {
-            return (s & 1) ? m + sm.m_off : b->at<float>(sm.o_mt);
-        };
-        for (const auto &ch : pl.x) {
-            xf.clear();
-            for (int i : ch) {
-                const auto &sm = b->samples[i];
-                xf.push_back({sm.g, src_of(sm), nullptr, b->at<float2>(sm.o_S1), (float)b->mat.Ms});
-            }
-            MM_TRY(bhip(b, mmk::launch_xfwd(xf.data(), (int)ch.size(), st), "batch xfwd"));
-        }
-        for (const auto &ch : pl.y) {
-            yd.clear();
-            for (int i : ch) {
-                const auto &sm = b->samples[i];
-                yd.push_back({sm.g, b->at<float2>(sm.o_S1), b->at<float2>(sm.o_S2)});
-            }
-            MM_TRY(bhip(b, mmk::launch_yfwd(yd.data(), (int)ch.size(), st), "batch yfwd"));
-        }
-        for (const auto &ch : pl.z) {
-            zc.clear();
-            for (int i : ch) {
-                const auto &sm = b->samples[i];
-                zc.push_back({sm.g, b->at<float2>(sm.o_S2), pl.K[i]});
-            }
-            MM_TRY(bhip(b, mmk::launch_zconv(zc.data(), (int)ch.size(), comp, st), "batch zconv"));
-        }
-        for (const auto &ch : pl.y) {
-            yd.clear();
-            for (int i : ch) {
-                const auto &sm = b->samples[i];
-                yd.push_back({sm.g, b->at<float2>(sm.o_S2), b->at<float2>(sm.o_S1)});
-            }
-            MM_TRY(bhip(b, mmk::launch_yinv(yd.data(), (int)ch.size(), st), "batch yinv"));
-        }
-        for (const auto &ch : pl.x) {
-            xi.clear();
-            for (int i : ch) {
-                const auto &sm = b->samples[i];
-                xi.push_back({sm.g, b->at<float2>(sm.o_S1), b->at<float>(sm.o_S2)});
-            }
-            MM_TRY(bhip(b, mmk::launch_xinv(xi.data(), (int)ch.size(), st), "batch xinv"));
-        }
-        for (const auto &ch : pl.loc) {
-            lc.clear();
-            for (int i : ch) {
-                const auto &sm = b->samples[i];
-                lc.push_back({sm.g, src_of(sm), b->at<float>(sm.o_S2), nullptr, nullptr, dst_of(sm), nullptr,
-                              (float)sm.h[0], (float)sm.h[1], (float)sm.h[2]});
-            }
-            MM_TRY(bhip(b, mmk::launch_local_batch(lc.data(), (int)ch.size(), p, MM_T_ALL, 1, (float)dt, renorm,
-                                                   flag, st),
-                        "batch local"));
-        }
+        const int par = (int)(s & 1);
+        for (const auto &L : b->launches)
+            if (L.pass == 0)
+                MM_TRY(bhip(b, mmk::launch_xfwd_table(table_of<mmk::XfwdDesc>(b, L, par), L.len, st, L.var), "batch xfwd"));
+        for (const auto &L : b->launches)
+            if (L.pass == 1)
+                MM_TRY(bhip(b, mmk::launch_yfwd_table(table_of<mmk::YDesc>(b, L, 0), L.len, st, L.var), "batch yfwd"));
+        for (const auto &L : b->launches)
+            if (L.pass == 2)
+                MM_TRY(bhip(b, mmk::launch_zconv_table(table_of<mmk::ZDesc>(b, L, 0), L.len, comp, st, L.var),
+                            "batch zconv"));
+        for (const auto &L : b->launches)
+            if (L.pass == 1)
+                MM_TRY(bhip(b, mmk::launch_yinv_table(table_of<mmk::YDesc>(b, L, 1), L.len, st, L.var), "batch yinv"));
+        for (const auto &L : b->launches)
+            if (L.pass == 0)
+                MM_TRY(bhip(b, mmk::launch_xinv_table(table_of<mmk::XinvDesc>(b, L, 2), L.len, st, L.var), "batch xinv"));
+        for (const auto &L : b->launches)
+            if (L.pass == 3)
+                MM_TRY(bhip(b, mmk::launch_local_table(table_of<mmk::LocalDesc>(b, L, par), L.len != 0, false, p,
+                                                       MM_T_ALL, 1, (float)dt, renorm, flag, st),
+                            "batch local"));
     }
-    if (nsteps & 1)
-        for (const auto &sm : b->samples)
-            MM_TRY(bhip(b, hipMemcpyAsync(m + sm.m_off, b->at<float>(sm.o_mt), sizeof(float) * 3 * sm.g.N,
-                                          hipMemcpyDeviceToDevice, st),
-                        "copy back state"));
     return MM_OK;
+}
+
+mm_status batch_copy_back(mm_batch *b, float *m)
+{
+    for (const auto &sm : b->samples)
+        MM_TRY(bhip(b, hipMemcpyAsync(m + sm.m_off, b->at<float>(sm.o_mt), sizeof(float) * 3 * sm.g.N,
+                                      hipMemcpyDeviceToDevice, b->stream),
+                    "copy back state"));
+    return MM_OK;
+}
+
+// FNV-1a over the sample sizes: the key of a batch's tuning in the cache file
+uint64_t batch_key(const mm_batch *b)
+{
+    uint64_t h = 1469598103934665603ULL;
+    auto mix = [&](uint64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (v >> (8 * k)) & 0xff;
+            h *= 1099511628211ULL;
+        }
+    };
+    mix(b->samples.size());
+    for (const auto &sm : b->samples) {
+        mix((uint64_t)sm.g.nx);
+        mix((uint64_t)sm.g.ny);
+        mix((uint64_t)sm.g.nz);
+    }
+    return h;
+}
+
+int tunable_launches(const mm_batch *b)
+{
+    int n = 0;
+    for (const auto &L : b->launches) n += L.pass < 3;
+    return n;
 }
 
 }  // namespace
@@ -1402,11 +1512,16 @@ mm_status mm_batch_create(mm_batch **out, int count, const int32_t *n, double dx
         b->groups[gi].members.push_back(i);
     }
     b->total_state = moff;
-    // workspace: spectra, flag, then per-sample buffers aliased with the
-    // tensor-build temporaries of the largest group
+    plan_launches(b);
+    // workspace: spectra, flag, launch plan, then per-sample buffers aliased
+    // with the tensor-build temporaries of the largest group
     Carve cv;
     for (auto &gr : b->groups) gr.o_K = cv.take(sizeof(float) * 6 * (size_t)gr.g.Hx * gr.g.Hy * gr.g.Hz);
     b->o_flag = cv.take(256);
+    b->o_plan = cv.off;
+    b->plan_bytes = plan_layout(b, b->o_plan);
+    cv.off = b->o_plan;
+    cv.take(b->plan_bytes);
     const size_t region = cv.off;
     Carve st;
     st.off = region;
@@ -1481,6 +1596,7 @@ mm_status mm_batch_set_workspace(mm_batch *b, void *dev_ptr, size_t bytes)
         return bfail(b, MM_ENOMEM, "workspace of %zu bytes is smaller than the %zu needed", bytes, b->total);
     b->ws = static_cast<char *>(dev_ptr);
     b->tensor = false;
+    b->plan_ok = false;
     b->drop_graphs();
     MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
     return bhip(b, hipMemsetAsync(b->at<int>(b->o_flag), 0, sizeof(int), b->stream), "clear flag");
@@ -1494,6 +1610,7 @@ mm_status mm_batch_set_material(mm_batch *b, const mm_material *m)
     if (s != MM_OK) return bfail(b, s, "%s", tmp.err.c_str());
     b->mat = tmp.mat;
     b->have_mat = true;
+    b->plan_ok = false;  // Ms is in the x-forward descriptors
     b->drop_graphs();
     return MM_OK;
 }
@@ -1506,6 +1623,7 @@ mm_status mm_batch_set_hext(mm_batch *b, const double *h)
         if (!std::isfinite(h[i])) return bfail(b, MM_EINVAL, "fields must be finite");
     for (size_t i = 0; i < b->samples.size(); ++i)
         for (int k = 0; k < 3; ++k) b->samples[i].h[k] = h[3 * i + k];
+    b->plan_ok = false;  // the fields are in the local descriptors
     b->drop_graphs();
     return MM_OK;
 }
@@ -1515,7 +1633,7 @@ mm_status mm_batch_build_tensor(mm_batch *b)
     if (!b) return MM_EINVAL;
     if (!b->ws) return bfail(b, MM_ESTATE, "no workspace set");
     MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
-    const size_t region = b->o_flag + 256;
+    const size_t region = b->o_plan + b->plan_bytes;
     for (auto &gr : b->groups) {
         const mmk::Geo &g = gr.g;
         Carve tb;
@@ -1545,8 +1663,12 @@ mm_status mm_batch_step(mm_batch *b, float *m, int64_t nsteps, double dt, uint32
     if (!b->have_mat) return bfail(b, MM_ESTATE, "material not set");
     if (!b->tensor) return bfail(b, MM_ESTATE, "mm_batch_build_tensor has not been called");
     MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
+    MM_TRY(plan_upload(b, m));
     const uint32_t sf = flags & ~uint32_t(MM_F_GRAPH);
-    if (!(flags & MM_F_GRAPH)) return batch_enqueue(b, m, nsteps, dt, sf);
+    if (!(flags & MM_F_GRAPH)) {
+        MM_TRY(batch_enqueue(b, nsteps, dt, sf));
+        return (nsteps & 1) ? batch_copy_back(b, m) : MM_OK;
+    }
     if (!b->stream) return bfail(b, MM_EINVAL, "MM_F_GRAPH needs a non-null stream");
     const int64_t chunk = nsteps >= kGraphChunk ? kGraphChunk : (nsteps & ~int64_t(1));
     int64_t done = 0;
@@ -1558,7 +1680,7 @@ mm_status mm_batch_step(mm_batch *b, float *m, int64_t nsteps, double dt, uint32
                 exec = b->graph_exec[k];
         if (!exec) {
             MM_TRY(bhip(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture"));
-            const mm_status s = batch_enqueue(b, m, chunk, dt, sf);
+            const mm_status s = batch_enqueue(b, chunk, dt, sf);
             hipGraph_t graph = nullptr;
             const hipError_t e_end = hipStreamEndCapture(b->stream, &graph);
             if (s != MM_OK) {
@@ -1575,7 +1697,164 @@ mm_status mm_batch_step(mm_batch *b, float *m, int64_t nsteps, double dt, uint32
         }
         for (; done + chunk <= nsteps; done += chunk) MM_TRY(bhip(b, hipGraphLaunch(exec, b->stream), "graph launch"));
     }
-    return batch_enqueue(b, m, nsteps - done, dt, sf);
+    MM_TRY(batch_enqueue(b, nsteps - done, dt, sf));
+    return ((nsteps - done) & 1) ? batch_copy_back(b, m) : MM_OK;
+}
+
+mm_status mm_batch_set_tuning(mm_batch *b, const int32_t *choices, int32_t n)
+{
+    if (!b) return MM_EINVAL;
+    if (!choices || n != tunable_launches(b))
+        return bfail(b, MM_EINVAL, "expected %d choices (x, y and z launches)", tunable_launches(b));
+    for (int k = 0; k < n; ++k)
+        if (choices[k] < 0 || choices[k] >= MM_TUNE_VARIANTS)
+            return bfail(b, MM_EINVAL, "tuning choice %d out of range [0, %d)", choices[k], MM_TUNE_VARIANTS);
+    int k = 0;
+    for (auto &L : b->launches) {
+        if (L.pass == 3) continue;
+        const int L1 = L.pass == 0 ? L.len / 2 : L.len;
+        L.var = mmk::pass_variant(L.pass, L1, choices[k++]);
+        L.width = launch_width(b, L, L.var);
+    }
+    b->drop_graphs();
+    return MM_OK;
+}
+
+mm_status mm_batch_get_tuning(const mm_batch *b, int32_t *choices, int32_t capacity, int32_t *n)
+{
+    if (!b || !n) return MM_EINVAL;
+    *n = tunable_launches(b);
+    if (choices && capacity < *n) return MM_EINVAL;
+    if (choices) {
+        int k = 0;
+        for (const auto &L : b->launches)
+            if (L.pass < 3) choices[k++] = L.var;
+    }
+    return MM_OK;
+}
+
+mm_status mm_batch_autotune(mm_batch *b, const char *cache_path, int32_t *choices, int32_t capacity, int32_t *n)
+{
+    if (!b) return MM_EINVAL;
+    if (!b->ws) return bfail(b, MM_ESTATE, "no workspace set");
+    if (!b->have_mat) return bfail(b, MM_ESTATE, "material not set");
+    if (!b->tensor) return bfail(b, MM_ESTATE, "mm_batch_build_tensor has not been called");
+    const int nl = tunable_launches(b);
+    if (n) *n = nl;
+    if (choices && capacity < nl) return bfail(b, MM_EINVAL, "choices holds %d entries, %d needed", capacity, nl);
+    MM_TRY(bhip(b, hipSetDevice(b->device), "hipSetDevice"));
+    hipDeviceProp_t prop;
+    MM_TRY(bhip(b, hipGetDeviceProperties(&prop, b->device), "device properties"));
+    std::string arch(prop.gcnArchName);
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    char key[32];
+    std::snprintf(key, sizeof key, "batch-%016llx", (unsigned long long)batch_key(b));
+    std::vector<int32_t> best(nl, 0);
+    bool found = false;
+    if (cache_path) {
+        if (FILE *f = std::fopen(cache_path, "r")) {
+            char a[256], k2[64];
+            int cnt = 0;
+            while (std::fscanf(f, "%255s %63s %d", a, k2, &cnt) == 3) {
+                std::vector<int32_t> v(cnt > 0 ? cnt : 0);
+                bool ok = cnt == nl;
+                for (int q = 0; q < cnt; ++q)
+                    if (std::fscanf(f, "%d", &v[q]) != 1 || v[q] < 0 || v[q] >= MM_TUNE_VARIANTS) ok = false;
+                if (ok && arch == a && std::string(k2) == key) {
+                    best = v;
+                    found = true;  // the last matching line wins
+                }
+            }
+            std::fclose(f);
+        }
+    }
+    if (!found) {
+        // time each variant of each launch on zeroed sample buffers: x
+        // launches as x-forward + x-inverse, y launches as forward + inverse,
+        // z launches alone
+        MM_TRY(bhip(b, hipStreamSynchronize(b->stream), "tune sync"));
+        for (const auto &sm : b->samples) {
+            MM_TRY(bhip(b, hipMemsetAsync(b->at<float>(sm.o_mt), 0, sizeof(float) * 3 * sm.g.N, b->stream), "clear"));
+            MM_TRY(bhip(b, hipMemsetAsync(b->at<float2>(sm.o_S1), 0, sizeof(float2) * 3 * sm.g.nz * sm.g.Hx * sm.g.ny,
+                                          b->stream), "clear"));
+            MM_TRY(bhip(b, hipMemsetAsync(b->at<float2>(sm.o_S2), 0, sizeof(float2) * 3 * sm.g.nz * sm.g.Hx * sm.g.Py,
+                                          b->stream), "clear"));
+        }
+        // the odd-step x-forward descriptors read the zeroed temporaries; the
+        // even-step set (for a state pointer that is not given here) is not
+        // launched, so any pointer serves as its base
+        float *mt0 = b->at<float>(b->samples[0].o_mt);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        MM_TRY(bhip(b, hipEventCreate(&e0), "event"));
+        if (hipEventCreate(&e1) != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return bfail(b, MM_EHIP, "event");
+        }
+        mm_status status = MM_OK;
+        int k = 0;
+        for (auto &L : b->launches) {
+            if (L.pass == 3 || status != MM_OK) continue;
+            const int L1 = L.pass == 0 ? L.len / 2 : L.len;
+            float best_t = 0.f;
+            for (int v = 0; v < MM_TUNE_VARIANTS && status == MM_OK; ++v) {
+                if (mmk::pass_variant(L.pass, L1, v) != v) continue;
+                L.var = v;
+                L.width = launch_width(b, L, v);
+                // the x-forward reads the temporaries through the odd-step set
+                status = plan_upload(b, mt0);
+                if (status != MM_OK) break;
+                auto launch = [&]() -> hipError_t {
+                    hipError_t e;
+                    if (L.pass == 0) {
+                        e = mmk::launch_xfwd_table(table_of<mmk::XfwdDesc>(b, L, 1), L.len, b->stream, v);
+                        if (e == hipSuccess) e = mmk::launch_xinv_table(table_of<mmk::XinvDesc>(b, L, 2), L.len, b->stream, v);
+                    } else if (L.pass == 1) {
+                        e = mmk::launch_yfwd_table(table_of<mmk::YDesc>(b, L, 0), L.len, b->stream, v);
+                        if (e == hipSuccess) e = mmk::launch_yinv_table(table_of<mmk::YDesc>(b, L, 1), L.len, b->stream, v);
+                    } else {
+                        e = mmk::launch_zconv_table(table_of<mmk::ZDesc>(b, L, 0), L.len, false, b->stream, v);
+                    }
+                    return e;
+                };
+                float t = 0.f;
+                hipError_t e = hipSuccess;
+                for (int r = 0; r < 2 && e == hipSuccess; ++r) e = launch();
+                if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+                for (int r = 0; r < 10 && e == hipSuccess; ++r) e = launch();
+                if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+                if (e != hipSuccess) {
+                    status = bhip(b, e, "batch autotune timing");
+                    break;
+                }
+                if (v == 0 || t < best_t) {
+                    best_t = t;
+                    best[k] = v;
+                }
+            }
+            ++k;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->plan_ok = false;  // the descriptors were written for the temporaries
+        if (status != MM_OK) return status;
+        if (cache_path) {
+            if (FILE *f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "%s %s %d", arch.c_str(), key, nl);
+                for (int q = 0; q < nl; ++q) std::fprintf(f, " %d", best[q]);
+                std::fprintf(f, "\n");
+                std::fclose(f);
+            } else {
+                return bfail(b, MM_EINVAL, "cannot append to the tuning cache %s", cache_path);
+            }
+        }
+    }
+    MM_TRY(mm_batch_set_tuning(b, best.data(), nl));
+    if (choices)
+        for (int q = 0; q < nl; ++q) choices[q] = best[q];
+    return MM_OK;
 }
 
 mm_status mm_batch_sync(mm_batch *b)

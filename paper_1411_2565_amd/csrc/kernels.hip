@@ -88,11 +88,6 @@ constexpr int kThreads = 256;
 #ifndef MMK_Y_NC
 #define MMK_Y_NC 1
 #endif
-// x-pass block order (see x_grid); rows first measured 2% faster on the
-// x-forward pass of the 256x256x32 block (17.6 vs 18.0 us)
-#ifndef MMK_X_ROWMAJOR
-#define MMK_X_ROWMAJOR 1
-#endif
 // lines per block of the x passes (16: 128-byte runs in the transposed S1)
 #ifndef MMK_X_LPB
 #define MMK_X_LPB 16
@@ -183,23 +178,57 @@ __device__ __forceinline__ void load_half_twiddles(float2 *tw)
 // E[k] = (Z[k] + conj Z[L-k])/2, O[k] = (Z[k] - conj Z[L-k])/(2i).
 // The half spectrum kx in [0, L] is written transposed, S1[c][z][kx][y].
 // ------------------------------------------------------------------------
-template <int L, int V, int NB>
-__global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xfwd(Batch<XfwdDesc, NB> B)
+// Block (row, tile) of an x pass: row = 3 z + c, tile = y tile.  Rows are the
+// fast index, so consecutive blocks (one per XCD in turn) are different rows
+// and, with a multiple of 8 rows, all tiles of a row land on one XCD (rows
+// first measured 2% faster on the x-forward of the 256x256x32 block).
+// The descriptor is copied whole (one batch of scalar loads) before any of
+// its fields decides anything.
+template <typename D, bool TAB>
+__device__ __forceinline__ D pass_desc(const PassArg<D, TAB> &A)
+{
+    D d;
+    if constexpr (TAB)
+        d = A.desc[blockIdx.y];
+    else
+        d = A.d;
+    // every field in scalar registers here: the loads of the whole
+    // descriptor issue together and complete at one wait, instead of one
+    // wait per field as the code first needs it
+    static_assert(sizeof(D) % 4 == 0, "descriptor of whole words");
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(&d);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(D) / 4); ++i) asm volatile("" ::"s"(w[i]));
+    return d;
+}
+template <typename D, bool TAB>
+__device__ __forceinline__ void x_block(const PassArg<D, TAB> &, const Geo &g, int &row, int &tile)
+{
+    if constexpr (TAB) {
+        const int rows = 3 * g.nz;
+        row = (int)(blockIdx.x % rows);
+        tile = (int)(blockIdx.x / rows);
+    } else {
+        row = blockIdx.x;
+        tile = blockIdx.y;
+    }
+}
+
+template <int L, int V, bool TAB>
+__global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xfwd(PassArg<XfwdDesc, TAB> A)
 {
     using S = XShape<L, V>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
-    const XfwdDesc &D = B.s[blockIdx.z];
+    const XfwdDesc D = pass_desc(A);
     const Geo &g = D.g;
+    int brow = 0, btile = 0;
+    x_block(A, g, brow, btile);
     const float *__restrict__ m = D.m;
     const float *__restrict__ ms_map = D.ms_map;
     const float ms = D.ms;
     float2 *__restrict__ S1 = D.S1;
-#if MMK_X_ROWMAJOR
-    const int c = blockIdx.x % 3, z = blockIdx.x / 3, y0 = blockIdx.y * LPB;
-#else
-    const int c = blockIdx.y % 3, z = blockIdx.y / 3, y0 = blockIdx.x * LPB;
-#endif
+    const int c = brow % 3, z = brow / 3, y0 = btile * LPB;
     if (z >= g.nz || y0 >= g.ny) return;
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
     const int y = y0 + ll;
@@ -292,24 +321,25 @@ __device__ __forceinline__ long long s2_line(long long line, const Geo &g)
 // a2 / a4: FFT along y of contiguous columns (length Py, ny non-zeros in /
 // ny kept out), one column per T threads.
 // ------------------------------------------------------------------------
-template <int L, int V, int NB>
-__global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
+template <int L, int V, bool TAB>
+__global__ __launch_bounds__(kThreads) void k_yfwd(PassArg<YDesc, TAB> A)
 {
     using S = YShape<L, V>;
     constexpr int E = S::E, T = S::T, NC = S::NC, LPB = S::LPB;
     extern __shared__ float2 sm[];
-    const YDesc &D = B.s[blockIdx.z];
+    const long long lb = blockIdx.x;
+    const YDesc D = pass_desc(A);
     const Geo &g = D.g;
     const float2 *__restrict__ S1 = D.in;
     float2 *__restrict__ S2 = D.out;
     const long long nlines = 3LL * g.nz * g.Hx;
-    if ((long long)blockIdx.x * LPB >= nlines) return;
+    if (lb * LPB >= nlines) return;
     const int gi = threadIdx.x / T, t = threadIdx.x - gi * T;
     float2 v[NC][E];
     float2 *lds[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        const long long line = lb * LPB + gi * NC + c;
         const bool ok = line < nlines;
         const float2 *in = S1 + line * g.ny;
 #pragma unroll
@@ -324,7 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
     reg_fft<L, false>(v, lds, t);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        const long long line = lb * LPB + gi * NC + c;
         if (line < nlines) {
             float2 *out = S2 + s2_line(line, g) * L;
 #pragma unroll
@@ -333,24 +363,25 @@ __global__ __launch_bounds__(kThreads) void k_yfwd(Batch<YDesc, NB> B)
     }
 }
 
-template <int L, int V, int NB>
-__global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
+template <int L, int V, bool TAB>
+__global__ __launch_bounds__(kThreads) void k_yinv(PassArg<YDesc, TAB> A)
 {
     using S = YShape<L, V>;
     constexpr int E = S::E, T = S::T, NC = S::NC, LPB = S::LPB;
     extern __shared__ float2 sm[];
-    const YDesc &D = B.s[blockIdx.z];
+    const long long lb = blockIdx.x;
+    const YDesc D = pass_desc(A);
     const Geo &g = D.g;
     const float2 *__restrict__ S2 = D.in;
     float2 *__restrict__ S1 = D.out;
     const long long nlines = 3LL * g.nz * g.Hx;
-    if ((long long)blockIdx.x * LPB >= nlines) return;
+    if (lb * LPB >= nlines) return;
     const int gi = threadIdx.x / T, t = threadIdx.x - gi * T;
     float2 v[NC][E];
     float2 *lds[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        const long long line = lb * LPB + gi * NC + c;
         const bool ok = line < nlines;
         const float2 *in = S2 + s2_line(line, g) * L;
 #pragma unroll
@@ -360,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_yinv(Batch<YDesc, NB> B)
     reg_fft<L, true, MMK_WAVE_FFT && (T <= 64)>(v, lds, t);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const long long line = (long long)blockIdx.x * LPB + gi * NC + c;
+        const long long line = lb * LPB + gi * NC + c;
         if (line < nlines) {
             float2 *out = S1 + line * g.ny;
 #pragma unroll
@@ -422,23 +453,31 @@ __device__ __forceinline__ int zc_tile(int slot, int ntiles)
     return r < 8 ? lower : ntiles - 1 - lower;
 }
 
-template <int L, bool COMP, int V, int NB>
-__global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, NB> B)
+template <int L, bool COMP, int V, bool TAB>
+__global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc, TAB> A)
 {
     using S = ZShape<L, V>;
     constexpr int E = S::E, T = S::T, CB = S::CB;
+    constexpr int NSUB = S::NSUB;
     extern __shared__ float2 sm[];
-    const ZDesc &D = B.s[blockIdx.z];
+    // block (slot, kx) of the sample's own grid of (column tiles, kx)
+    const ZDesc D = pass_desc(A);
     const Geo &g = D.g;
+    int slot, kx, nst;
+    if constexpr (TAB) {
+        nst = (g.Py + CB * NSUB - 1) / (CB * NSUB);
+        slot = (int)(blockIdx.x % nst);
+        kx = (int)(blockIdx.x / nst);
+    } else {
+        slot = blockIdx.x;
+        kx = blockIdx.y;
+        nst = gridDim.x;
+    }
     float2 *__restrict__ S2 = D.S2;
     const float *__restrict__ K = D.K;
-    constexpr int NSUB = S::NSUB;
     const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
-    const int kx = blockIdx.y;
-    const int stile = zc_tile(blockIdx.x, gridDim.x);
-    // a batch launch covers the largest sample: whole tiles beyond this one
-    // leave (block-uniform, before any barrier)
-    if (kx >= g.Hx || stile * NSUB * CB >= g.Py) return;
+    const int stile = zc_tile(slot, nst);
+    if (kx >= g.Hx || stile * NSUB * CB >= g.Py) return;  // block-uniform, before any barrier
     // every exchange of an FFT ends with a block barrier after its LDS
     // reads, so the next tile's first LDS writes cannot overtake them
     for (int sub = 0; sub < NSUB; ++sub) {
@@ -515,21 +554,19 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(Batch<ZDesc, 
 // exp(+2 pi i k/Px); the unnormalised inverse length-L FFT of Z' is
 // x[2n] + i x[2n+1].
 // ------------------------------------------------------------------------
-template <int L, int V, int NB>
-__global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(Batch<XinvDesc, NB> B)
+template <int L, int V, bool TAB>
+__global__ __launch_bounds__((XShape<L, V>::THREADS)) void k_xinv(PassArg<XinvDesc, TAB> A)
 {
     using S = XShape<L, V>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, LD = lds_line(L);
     extern __shared__ float2 sm[];
-    const XinvDesc &D = B.s[blockIdx.z];
+    const XinvDesc D = pass_desc(A);
     const Geo &g = D.g;
+    int row = 0, btile = 0;
+    x_block(A, g, row, btile);
     const float2 *__restrict__ S1 = D.S1;
     float *__restrict__ Hd = D.Hd;
-#if MMK_X_ROWMAJOR
-    const int c = blockIdx.x % 3, z = blockIdx.x / 3, y0 = blockIdx.y * LPB;
-#else
-    const int c = blockIdx.y % 3, z = blockIdx.y / 3, y0 = blockIdx.x * LPB;
-#endif
+    const int c = row % 3, z = row / 3, y0 = btile * LPB;
     if (z >= g.nz || y0 >= g.ny) return;
     const int nl = min(LPB, g.ny - y0);
     const float2 *in = S1 + ((long long)(c * g.nz + z) * g.Hx) * g.ny + y0;
@@ -663,11 +700,12 @@ static int local_perm_q(const Geo &g, long long cells, long long nb)
 
 // MAPPED: the samples carry an Ms map (per-cell Ms, and vacuum where it is 0);
 // without one the kernel compiles to the uniform-Ms code alone.
-template <int MODE, int V, int NB, bool MAPPED>
-__global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, LocalParams p, uint32_t terms,
+template <int MODE, int V, bool TAB, bool MAPPED>
+__global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, LocalParams p, uint32_t terms,
                                                     float dt, int renorm, int *__restrict__ flag)
 {
-    const LocalDesc &D = B.s[blockIdx.z];
+    const long long lb = blockIdx.x;
+    const LocalDesc D = pass_desc(A);
     const Geo &g = D.g;
     const float *__restrict__ m = D.m;
     const float *__restrict__ Hd = D.Hd;
@@ -681,9 +719,9 @@ __global__ __launch_bounds__(kThreads) void k_local(Batch<LocalDesc, NB> B, Loca
     if (p.sched) {
         const double t = p.clk[p.tslot];
         hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
-        if (MODE == 1 && blockIdx.x == 0 && blockIdx.z == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
+        if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
     }
-    const long long i0 = ((long long)local_block(blockIdx.x, D.perm_q) * kThreads + threadIdx.x) * V;
+    const long long i0 = ((long long)local_block((int)lb, D.perm_q) * kThreads + threadIdx.x) * V;
     if (i0 >= g.N) return;
     const long long N = g.N;
     const int x0 = (int)(i0 % g.nx);
@@ -1400,38 +1438,6 @@ __global__ __launch_bounds__(kThreads) void k_pack(Geo g, const double *__restri
 
 #define MM_LEN_CASES(X) X(1) X(2) X(4) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024)
 
-template <typename Dsc, int NB>
-static Batch<Dsc, NB> pack(const Dsc *d, int count)
-{
-    Batch<Dsc, NB> b{};
-    for (int i = 0; i < count && i < NB; ++i) b.s[i] = d[i];
-    return b;
-}
-
-// grid extents over a batch of samples with a common padded size
-struct Extent {
-    int ny = 0, nz = 0, Py = 0, Hx = 0;
-    long long lines = 0, items = 0;
-};
-template <typename Dsc>
-static Extent extent(const Dsc *d, int count)
-{
-    Extent e;
-    for (int i = 0; i < count; ++i) {
-        const Geo &g = d[i].g;
-        e.ny = g.ny > e.ny ? g.ny : e.ny;
-        e.nz = g.nz > e.nz ? g.nz : e.nz;
-        e.Py = g.Py > e.Py ? g.Py : e.Py;
-        e.Hx = g.Hx > e.Hx ? g.Hx : e.Hx;
-        const long long l = 3LL * g.nz * g.Hx;
-        e.lines = l > e.lines ? l : e.lines;
-        const long long it = (g.nx % 4 == 0) ? g.N / 4 : g.N;
-        e.items = it > e.items ? it : e.items;
-    }
-    return e;
-}
-
-// one launch for 1 sample or up to kMaxBatch samples
 // Start/stop events for the next timed launch on this host thread.  The
 // dispatch records them itself (hipExtLaunchKernelGGL), so their interval is
 // the kernel's own execution, as a profiler's kernel trace reports it, without
@@ -1459,75 +1465,98 @@ void clear_launch_events() { t_ev_start = t_ev_stop = nullptr; }
         }                                                                                   \
     } while (0)
 
-#define MM_BATCH_LAUNCH(KERNEL, DESC, GRID, BLOCK, LDS, STREAM, ...)                           \
-    do {                                                                                    \
-        if (count == 1)                                                                     \
-            MMK_LAUNCH((KERNEL<__VA_ARGS__, 1>), GRID, BLOCK, LDS, STREAM,                  \
-                       pack<DESC, 1>(d, count));                                            \
-        else                                                                                \
-            MMK_LAUNCH((KERNEL<__VA_ARGS__, kMaxBatch>), GRID, BLOCK, LDS, STREAM,          \
-                       pack<DESC, kMaxBatch>(d, count));                                    \
-    } while (0)
-
-// Runs go(integral_constant<int, V>) for the variant to use: `var` for a
-// single sample with L >= kTuneMinL, V = 0 otherwise.
+// Runs go(integral_constant<int, V>) for the variant to use: `var` for lines
+// of kTuneMinL points or more, V = 0 otherwise.
 template <int LL, typename F>
-static void with_variant(int var, int count, F &&go)
+static void with_variant(int var, F &&go)
 {
     if constexpr (LL >= kTuneMinL) {
-        if (count == 1 && var == 1) return go(std::integral_constant<int, 1>{});
-        if (count == 1 && var == 2) return go(std::integral_constant<int, 2>{});
+        if (var == 1) return go(std::integral_constant<int, 1>{});
+        if (var == 2) return go(std::integral_constant<int, 2>{});
     }
     go(std::integral_constant<int, 0>{});
 }
 
-// one launch of a pass kernel: KERNEL<ARGS..., V, NB>, NB = 1 for a single
-// sample, kMaxBatch (only with V = 0) for a batch
-#define MM_PASS_LAUNCH(KERNEL, DESC, GRID, BLOCK, LDS, STREAM, VV, ...)                        \
-    do {                                                                                    \
-        if (count == 1) {                                                                   \
-            MMK_LAUNCH((KERNEL<__VA_ARGS__, VV, 1>), GRID, BLOCK, LDS, STREAM, pack<DESC, 1>(d, count)); \
-        } else {                                                                            \
-            if constexpr (VV == 0)                                                          \
-                MMK_LAUNCH((KERNEL<__VA_ARGS__, 0, kMaxBatch>), GRID, BLOCK, LDS, STREAM,   \
-                           pack<DESC, kMaxBatch>(d, count));                                \
-        }                                                                                   \
-    } while (0)
-
-// x-pass grid: (y tiles, component-z rows), or with MMK_X_ROWMAJOR rows first
-// so that consecutive blocks (one per XCD in turn) are different rows and all
-// tiles of a row land on one XCD
-static dim3 x_grid(unsigned tiles, unsigned rows, int count)
+int pass_variant(int pass, int L, int var)
 {
-#if MMK_X_ROWMAJOR
-    return dim3(rows, tiles, count);
-#else
-    return dim3(tiles, rows, count);
-#endif
+    (void)pass;
+    return (L >= kTuneMinL && var >= 0 && var < kVariants) ? var : 0;
 }
 
-template <typename Dsc>
-static bool same_px(const Dsc *d, int count)
+// Per-sample grids.  x passes: (3 nz rows, y tiles); y passes: line blocks;
+// z pass: (column tiles, kx); all shapes from the structs above.
+template <int LL>
+static long long x_blocks(const Geo &g, int var)
 {
-    for (int i = 1; i < count; ++i)
-        if (d[i].g.Px != d[0].g.Px) return false;
-    return true;
+    long long n = 0;
+    with_variant<LL>(var, [&](auto vt) {
+        using S = XShape<LL, decltype(vt)::value>;
+        n = 3LL * g.nz * ((g.ny + S::LPB - 1) / S::LPB);
+    });
+    return n;
+}
+template <int LL>
+static long long y_blocks(const Geo &g, int var)
+{
+    long long n = 0;
+    with_variant<LL>(var, [&](auto vt) {
+        using S = YShape<LL, decltype(vt)::value>;
+        n = (3LL * g.nz * g.Hx + S::LPB - 1) / S::LPB;
+    });
+    return n;
+}
+template <int LL>
+static long long z_blocks(const Geo &g, int var)
+{
+    long long n = 0;
+    with_variant<LL>(var, [&](auto vt) {
+        using S = ZShape<LL, decltype(vt)::value>;
+        constexpr int CT = S::CB * S::NSUB;
+        n = (long long)((g.Py + CT - 1) / CT) * g.Hx;
+    });
+    return n;
 }
 
-hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var)
+long long pass_blocks(int pass, const Geo &g, int var)
 {
-    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants || !same_px(d, count))
-        return hipErrorInvalidValue;
-    const Extent e = extent(d, count);
-    switch (d[0].g.Px / 2) {
+    const int L = pass == 0 ? g.Px / 2 : (pass == 1 ? g.Py : g.Pz);
+    switch (L) {
+#define CASE(LL)                                                                              \
+    case LL:                                                                                  \
+        if constexpr (LL <= 512) {                                                            \
+            if (pass == 0) return x_blocks<LL>(g, var);                                       \
+        }                                                                                     \
+        if (pass == 1) return y_blocks<LL>(g, var);                                           \
+        return z_blocks<LL>(g, var);
+        MM_LEN_CASES(CASE)
+#undef CASE
+    default:
+        return -1;
+    }
+}
+
+long long local_blocks(const Geo &g, bool vec)
+{
+    const long long items = vec ? g.N / 4 : g.N;
+    return (items + kThreads - 1) / kThreads;
+}
+
+int local_perm(const Geo &g, bool vec) { return local_perm_q(g, (long long)kThreads * (vec ? 4 : 1), local_blocks(g, vec)); }
+
+// ---- single sample: descriptor by value, the sample's own grid
+
+hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s, int var)
+{
+    const PassArg<XfwdDesc, false> a{{g, m, ms_map, S1, ms}};
+    switch (g.Px / 2) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         if constexpr (LL <= 512) {                                                            \
-            with_variant<LL>(var, count, [&](auto vt) {                                       \
-                constexpr int VV = decltype(vt)::value;                                       \
-                using S = XShape<LL, VV>;                                                     \
-                dim3 grid = x_grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);            \
-                MM_PASS_LAUNCH(k_xfwd, XfwdDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, VV, LL); \
+            with_variant<LL>(var, [&](auto vt) {                                              \
+                using S = XShape<LL, decltype(vt)::value>;                                    \
+                dim3 grid(3 * g.nz, (g.ny + S::LPB - 1) / S::LPB);                            \
+                MMK_LAUNCH((k_xfwd<LL, decltype(vt)::value, false>), grid, dim3(S::THREADS),  \
+                           S::LDS * sizeof(float2), s, a);                                    \
             });                                                                               \
         }                                                                                     \
         break;                                                                                \
@@ -1540,20 +1569,18 @@ hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var)
     return hipGetLastError();
 }
 
-hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var)
+hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants || !same_px(d, count))
-        return hipErrorInvalidValue;
-    const Extent e = extent(d, count);
-    switch (d[0].g.Px / 2) {
+    const PassArg<XinvDesc, false> a{{g, S1, Hd}};
+    switch (g.Px / 2) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         if constexpr (LL <= 512) {                                                            \
-            with_variant<LL>(var, count, [&](auto vt) {                                       \
-                constexpr int VV = decltype(vt)::value;                                       \
-                using S = XShape<LL, VV>;                                                     \
-                dim3 grid = x_grid((e.ny + S::LPB - 1) / S::LPB, 3 * e.nz, count);            \
-                MM_PASS_LAUNCH(k_xinv, XinvDesc, grid, dim3(S::THREADS), S::LDS * sizeof(float2), s, VV, LL); \
+            with_variant<LL>(var, [&](auto vt) {                                              \
+                using S = XShape<LL, decltype(vt)::value>;                                    \
+                dim3 grid(3 * g.nz, (g.ny + S::LPB - 1) / S::LPB);                            \
+                MMK_LAUNCH((k_xinv<LL, decltype(vt)::value, false>), grid, dim3(S::THREADS),  \
+                           S::LDS * sizeof(float2), s, a);                                    \
             });                                                                               \
         }                                                                                     \
         break;                                                                                \
@@ -1566,23 +1593,21 @@ hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var)
     return hipGetLastError();
 }
 
-static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t s, int var)
+static hipError_t launch_y(const Geo &g, const float2 *in, float2 *out, bool inverse, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
-    for (int i = 1; i < count; ++i)
-        if (d[i].g.Py != d[0].g.Py) return hipErrorInvalidValue;
-    const Extent e = extent(d, count);
-    switch (d[0].g.Py) {
+    const PassArg<YDesc, false> a{{g, in, out}};
+    switch (g.Py) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
-        with_variant<LL>(var, count, [&](auto vt) {                                           \
-            constexpr int VV = decltype(vt)::value;                                           \
-            using S = YShape<LL, VV>;                                                         \
-            dim3 grid((unsigned)((e.lines + S::LPB - 1) / S::LPB), 1, count);                \
+        with_variant<LL>(var, [&](auto vt) {                                                  \
+            using S = YShape<LL, decltype(vt)::value>;                                        \
+            dim3 grid((unsigned)((3LL * g.nz * g.Hx + S::LPB - 1) / S::LPB));                \
             if (inverse)                                                                      \
-                MM_PASS_LAUNCH(k_yinv, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, VV, LL); \
+                MMK_LAUNCH((k_yinv<LL, decltype(vt)::value, false>), grid, dim3(kThreads),    \
+                           S::LDS * sizeof(float2), s, a);                                    \
             else                                                                              \
-                MM_PASS_LAUNCH(k_yfwd, YDesc, grid, dim3(kThreads), S::LDS * sizeof(float2), s, VV, LL); \
+                MMK_LAUNCH((k_yfwd<LL, decltype(vt)::value, false>), grid, dim3(kThreads),    \
+                           S::LDS * sizeof(float2), s, a);                                    \
         });                                                                                   \
         break;                                                                                \
     }
@@ -1594,29 +1619,32 @@ static hipError_t launch_y(const YDesc *d, int count, bool inverse, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s, int var) { return launch_y(d, count, false, s, var); }
-hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s, int var) { return launch_y(d, count, true, s, var); }
-
-hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s, int var)
+hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s, int var)
 {
-    if (count < 1 || count > kMaxBatch || var < 0 || var >= kVariants) return hipErrorInvalidValue;
-    const Geo &g = d[0].g;
-    const Extent e = extent(d, count);  // samples may differ in Py and Hx, not in Pz
-    for (int i = 1; i < count; ++i)
-        if (d[i].g.Pz != g.Pz) return hipErrorInvalidValue;
+    return launch_y(g, S1, S2, false, s, var);
+}
+hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s, int var)
+{
+    return launch_y(g, S2, S1, true, s, var);
+}
+
+hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s, int var)
+{
+    const PassArg<ZDesc, false> a{{g, S2, K}};
     switch (g.Pz) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
-        with_variant<LL>(comp ? 0 : var, count, [&](auto vt) {                                \
+        with_variant<LL>(comp ? 0 : var, [&](auto vt) {                                       \
             constexpr int VV = decltype(vt)::value;                                           \
             using S = ZShape<LL, VV>;                                                         \
             constexpr int CT = S::CB * S::NSUB;                                               \
-            dim3 grid((e.Py + CT - 1) / CT, e.Hx, count);                                     \
+            dim3 grid((g.Py + CT - 1) / CT, g.Hx);                                            \
             const size_t lds = S::LDS * sizeof(float2);                                       \
             if (comp) {                                                                       \
-                if constexpr (VV == 0) MM_PASS_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, 0, LL, true); \
+                if constexpr (VV == 0)                                                        \
+                    MMK_LAUNCH((k_zconv<LL, true, 0, false>), grid, dim3(S::THREADS), lds, s, a); \
             } else {                                                                          \
-                MM_PASS_LAUNCH(k_zconv, ZDesc, grid, dim3(S::THREADS), lds, s, VV, LL, false); \
+                MMK_LAUNCH((k_zconv<LL, false, VV, false>), grid, dim3(S::THREADS), lds, s, a); \
             }                                                                                 \
         });                                                                                   \
         break;                                                                                \
@@ -1629,43 +1657,152 @@ hipError_t launch_zconv(const ZDesc *d, int count, bool comp, hipStream_t s, int
     return hipGetLastError();
 }
 
-hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &p, uint32_t terms, int mode,
-                              float dt, int renorm, int *flag, hipStream_t s)
+// ---- many samples: descriptors and block map in device memory
+
+template <typename Dsc>
+static PassArg<Dsc, true> targ(const Table<Dsc> &t)
 {
-    if (count < 1 || count > kMaxBatch) return hipErrorInvalidValue;
-    bool vec = true;
-    for (int i = 0; i < count; ++i) vec = vec && (d[i].g.nx % 4 == 0);
-    long long items = 0;
-    for (int i = 0; i < count; ++i) {
-        const long long it = vec ? d[i].g.N / 4 : d[i].g.N;
-        items = it > items ? it : items;
+    return PassArg<Dsc, true>{t.desc};
+}
+
+template <typename Dsc>
+static bool table_ok(const Table<Dsc> &t)
+{
+    return t.desc && t.width >= 1 && t.width <= 0x7fffffffLL && t.count >= 1 && t.count <= 65535;
+}
+
+template <typename Dsc>
+static dim3 tgrid(const Table<Dsc> &t)
+{
+    return dim3((unsigned)t.width, (unsigned)t.count);
+}
+
+hipError_t launch_xfwd_table(const Table<XfwdDesc> &t, int Px, hipStream_t s, int var)
+{
+    if (!table_ok(t)) return hipErrorInvalidValue;
+    const auto a = targ(t);
+    switch (Px / 2) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        if constexpr (LL <= 512) {                                                            \
+            with_variant<LL>(var, [&](auto vt) {                                              \
+                using S = XShape<LL, decltype(vt)::value>;                                    \
+                MMK_LAUNCH((k_xfwd<LL, decltype(vt)::value, true>), tgrid(t), \
+                           dim3(S::THREADS), S::LDS * sizeof(float2), s, a);                  \
+            });                                                                               \
+        }                                                                                     \
+        break;                                                                                \
     }
-    dim3 grid((unsigned)((items + kThreads - 1) / kThreads), 1, count);
-    bool mapped = false;
-    for (int i = 0; i < count; ++i) mapped = mapped || d[i].ms_map != nullptr;
-    LocalDesc dq[kMaxBatch];
-    for (int i = 0; i < count; ++i) {
-        dq[i] = d[i];
-        dq[i].perm_q = local_perm_q(d[i].g, (long long)kThreads * (vec ? 4 : 1), grid.x);
+        MM_LEN_CASES(CASE)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
     }
-    d = dq;
+    return hipGetLastError();
+}
+
+hipError_t launch_xinv_table(const Table<XinvDesc> &t, int Px, hipStream_t s, int var)
+{
+    if (!table_ok(t)) return hipErrorInvalidValue;
+    const auto a = targ(t);
+    switch (Px / 2) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        if constexpr (LL <= 512) {                                                            \
+            with_variant<LL>(var, [&](auto vt) {                                              \
+                using S = XShape<LL, decltype(vt)::value>;                                    \
+                MMK_LAUNCH((k_xinv<LL, decltype(vt)::value, true>), tgrid(t), \
+                           dim3(S::THREADS), S::LDS * sizeof(float2), s, a);                  \
+            });                                                                               \
+        }                                                                                     \
+        break;                                                                                \
+    }
+        MM_LEN_CASES(CASE)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_y_table(const Table<YDesc> &t, int Py, bool inverse, hipStream_t s, int var)
+{
+    if (!table_ok(t)) return hipErrorInvalidValue;
+    const auto a = targ(t);
+    switch (Py) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        with_variant<LL>(var, [&](auto vt) {                                                  \
+            using S = YShape<LL, decltype(vt)::value>;                                        \
+            if (inverse)                                                                      \
+                MMK_LAUNCH((k_yinv<LL, decltype(vt)::value, true>), tgrid(t), \
+                           dim3(kThreads), S::LDS * sizeof(float2), s, a);                    \
+            else                                                                              \
+                MMK_LAUNCH((k_yfwd<LL, decltype(vt)::value, true>), tgrid(t), \
+                           dim3(kThreads), S::LDS * sizeof(float2), s, a);                    \
+        });                                                                                   \
+        break;                                                                                \
+    }
+        MM_LEN_CASES(CASE)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_yfwd_table(const Table<YDesc> &t, int Py, hipStream_t s, int var)
+{
+    return launch_y_table(t, Py, false, s, var);
+}
+hipError_t launch_yinv_table(const Table<YDesc> &t, int Py, hipStream_t s, int var)
+{
+    return launch_y_table(t, Py, true, s, var);
+}
+
+hipError_t launch_zconv_table(const Table<ZDesc> &t, int Pz, bool comp, hipStream_t s, int var)
+{
+    if (!table_ok(t)) return hipErrorInvalidValue;
+    const auto a = targ(t);
+    switch (Pz) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        with_variant<LL>(comp ? 0 : var, [&](auto vt) {                                       \
+            constexpr int VV = decltype(vt)::value;                                           \
+            using S = ZShape<LL, VV>;                                                         \
+            const size_t lds = S::LDS * sizeof(float2);                                       \
+            if (comp) {                                                                       \
+                if constexpr (VV == 0)                                                        \
+                    MMK_LAUNCH((k_zconv<LL, true, 0, true>), tgrid(t),       \
+                               dim3(S::THREADS), lds, s, a);                                  \
+            } else {                                                                          \
+                MMK_LAUNCH((k_zconv<LL, false, VV, true>), tgrid(t),         \
+                           dim3(S::THREADS), lds, s, a);                                      \
+            }                                                                                 \
+        });                                                                                   \
+        break;                                                                                \
+    }
+        MM_LEN_CASES(CASE)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---- local kernel
+
+template <bool TAB>
+static hipError_t launch_local_any(const PassArg<LocalDesc, TAB> &a, dim3 grid, bool vec, bool mapped,
+                                   const LocalParams &p, uint32_t terms, int mode, float dt, int renorm,
+                                   int *flag, hipStream_t s)
+{
 #define LOCAL(MODE, V)                                                                        \
     do {                                                                                      \
-        if (count == 1) {                                                                     \
-            if (mapped)                                                                       \
-                MMK_LAUNCH((k_local<MODE, V, 1, true>), grid, dim3(kThreads), 0, s,           \
-                           pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);         \
-            else                                                                              \
-                MMK_LAUNCH((k_local<MODE, V, 1, false>), grid, dim3(kThreads), 0, s,          \
-                           pack<LocalDesc, 1>(d, count), p, terms, dt, renorm, flag);         \
-        } else {                                                                              \
-            if (mapped)                                                                       \
-                MMK_LAUNCH((k_local<MODE, V, kMaxBatch, true>), grid, dim3(kThreads), 0, s,   \
-                           pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
-            else                                                                              \
-                MMK_LAUNCH((k_local<MODE, V, kMaxBatch, false>), grid, dim3(kThreads), 0, s,  \
-                           pack<LocalDesc, kMaxBatch>(d, count), p, terms, dt, renorm, flag); \
-        }                                                                                     \
+        if (mapped)                                                                           \
+            MMK_LAUNCH((k_local<MODE, V, TAB, true>), grid, dim3(kThreads), 0, s, a, p, terms, dt, renorm, flag); \
+        else                                                                                  \
+            MMK_LAUNCH((k_local<MODE, V, TAB, false>), grid, dim3(kThreads), 0, s, a, p, terms, dt, renorm, flag); \
     } while (0)
     if (mode == 0) {
         if (vec) LOCAL(0, 4); else LOCAL(0, 1);
@@ -1678,32 +1815,21 @@ hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &
     return hipGetLastError();
 }
 
-// ---- single-sample forms
-hipError_t launch_xfwd(const Geo &g, const float *m, const float *ms_map, float ms, float2 *S1, hipStream_t s,
-                       int var)
+hipError_t launch_local_table(const Table<LocalDesc> &t, bool vec, bool mapped, const LocalParams &p,
+                              uint32_t terms, int mode, float dt, int renorm, int *flag, hipStream_t s)
 {
-    XfwdDesc d{g, m, ms_map, S1, ms};
-    return launch_xfwd(&d, 1, s, var);
+    if (!table_ok(t)) return hipErrorInvalidValue;
+    return launch_local_any(targ(t), tgrid(t), vec, mapped, p, terms, mode, dt, renorm, flag, s);
 }
-hipError_t launch_yfwd(const Geo &g, const float2 *S1, float2 *S2, hipStream_t s, int var)
+
+static hipError_t launch_local_one(LocalDesc d, const LocalParams &p, uint32_t terms, int mode, float dt,
+                                   int renorm, int *flag, hipStream_t s)
 {
-    YDesc d{g, S1, S2};
-    return launch_yfwd(&d, 1, s, var);
-}
-hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hipStream_t s, int var)
-{
-    ZDesc d{g, S2, K};
-    return launch_zconv(&d, 1, comp, s, var);
-}
-hipError_t launch_yinv(const Geo &g, const float2 *S2, float2 *S1, hipStream_t s, int var)
-{
-    YDesc d{g, S2, S1};
-    return launch_yinv(&d, 1, s, var);
-}
-hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s, int var)
-{
-    XinvDesc d{g, S1, Hd};
-    return launch_xinv(&d, 1, s, var);
+    const bool vec = d.g.nx % 4 == 0;
+    d.perm_q = local_perm(d.g, vec);
+    const PassArg<LocalDesc, false> a{d};
+    return launch_local_any(a, dim3((unsigned)local_blocks(d.g, vec)), vec, d.ms_map != nullptr, p, terms, mode, dt,
+                            renorm, flag, s);
 }
 
 hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
@@ -1711,7 +1837,7 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
                         int renorm, float *out_m, float *out_h, int *flag, hipStream_t s)
 {
     LocalDesc d{g, m, Hd, ms_map, h_map, out_m, out_h, p.h0, p.h1, p.h2};
-    return launch_local_batch(&d, 1, p, terms, mode, dt, renorm, flag, s);
+    return launch_local_one(d, p, terms, mode, dt, renorm, flag, s);
 }
 
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,
@@ -1719,7 +1845,7 @@ hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, cons
                         int renorm, float *out_m, int *flag, hipStream_t s)
 {
     LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc, eacc, kbuf};
-    return launch_local_batch(&d, 1, p, 15u, 2, dt, renorm, flag, s);
+    return launch_local_one(d, p, 15u, 2, dt, renorm, flag, s);
 }
 
 // Maximum of n non-negative floats (NaN propagates): grid-stride loop, LDS

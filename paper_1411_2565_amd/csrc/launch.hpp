@@ -42,10 +42,7 @@ struct LocalParams {
     double t_start, t_decay, t_stop, dt64;
 };
 
-// Per-sample arguments of one pass.  A launch processes up to kMaxBatch
-// samples of one padded size; the descriptors travel by value in the kernel
-// arguments and blockIdx.z selects the sample.
-constexpr int kMaxBatch = 64;
+// Per-sample arguments of one pass.
 struct XfwdDesc {
     Geo g;
     const float *m;       // state [3][nz][ny][nx]
@@ -80,16 +77,34 @@ struct LocalDesc {
     float *kbuf;          // mode 2: stored slopes k_0, k_1, ... (3N floats each) for tableaus with full rows
     int perm_q;           // set by the launcher: blocks per XCD per z-plane of the block order (0: launch order)
 };
-template <typename D, int NB>
-struct Batch {
-    D s[NB];
+// Where a pass kernel finds its sample and its block within the sample.
+//   TAB = false: one sample, its descriptor by value, the grid is the
+//     sample's own (2-D for the x and z passes).
+//   TAB = true: many samples; their descriptors live in device memory and
+//     the grid is (blocks, samples): blockIdx.y is the sample, blockIdx.x
+//     the block within that sample's own grid, flattened x-fastest.  The
+//     grid is as wide as the launch's largest sample (a multiple of 8, so
+//     every sample starts on the same XCD); a block beyond its sample's own
+//     grid exits after reading the descriptor.
+template <typename D, bool TAB>
+struct PassArg;
+template <typename D>
+struct PassArg<D, false> {
+    D d;
 };
-// Batched descriptors travel by value in the kernel arguments; by-value
-// arguments of up to 20.8 KB were checked to arrive intact on gfx950.
-static_assert(sizeof(Batch<LocalDesc, kMaxBatch>) + sizeof(LocalParams) + 64 <= 20800, "batch arguments too large");
-static_assert(sizeof(Batch<XfwdDesc, kMaxBatch>) <= 20800 && sizeof(Batch<XinvDesc, kMaxBatch>) <= 20800 &&
-                  sizeof(Batch<YDesc, kMaxBatch>) <= 20800 && sizeof(Batch<ZDesc, kMaxBatch>) <= 20800,
-              "batch arguments too large");
+template <typename D>
+struct PassArg<D, true> {
+    const D *desc;
+};
+
+// A table launch: `count` descriptors in device memory, `width` blocks per
+// sample (the grid is width x count).
+template <typename D>
+struct Table {
+    const D *desc;
+    long long width;
+    int count;
+};
 
 // FP64 energy coefficients.
 struct EnergyParams {
@@ -114,18 +129,31 @@ constexpr long long kScratchPartials = 4096;
 // address of the static scratch array on this device
 hipError_t init_tables(hipStream_t s, double **scratch_dev);
 
-// demag pipeline, batched: `count` (1..kMaxBatch) samples sharing Px, Py, Pz
-// Pass launchers.  `var` selects a launch-shape variant (0 = default, 1, 2;
-// see the shape structs in kernels.hip) for single-sample launches with
-// lines of 64 points or more; other launches use 0.
-hipError_t launch_xfwd(const XfwdDesc *d, int count, hipStream_t s, int var = 0);
-hipError_t launch_yfwd(const YDesc *d, int count, hipStream_t s, int var = 0);
-hipError_t launch_zconv(const ZDesc *d, int count, bool compensated, hipStream_t s, int var = 0);
-hipError_t launch_yinv(const YDesc *d, int count, hipStream_t s, int var = 0);
-hipError_t launch_xinv(const XinvDesc *d, int count, hipStream_t s, int var = 0);
-// local terms + Euler step (mode 1) or field output (mode 0), batched
-hipError_t launch_local_batch(const LocalDesc *d, int count, const LocalParams &p, uint32_t terms, int mode,
-                              float dt, int renorm, int *flag, hipStream_t s);
+// Table launches of many samples.  Every sample of one launch has the
+// transform length given (x: Px, y: Py, z: Pz); `var` selects a
+// launch-shape variant (0 = default, 1, 2; see the shape structs in
+// kernels.hip) for lines of 64 points or more, 0 otherwise, and the block map
+// must be at least the largest sample's pass_blocks for that variant.
+hipError_t launch_xfwd_table(const Table<XfwdDesc> &t, int Px, hipStream_t s, int var = 0);
+hipError_t launch_yfwd_table(const Table<YDesc> &t, int Py, hipStream_t s, int var = 0);
+hipError_t launch_zconv_table(const Table<ZDesc> &t, int Pz, bool compensated, hipStream_t s, int var = 0);
+hipError_t launch_yinv_table(const Table<YDesc> &t, int Py, hipStream_t s, int var = 0);
+hipError_t launch_xinv_table(const Table<XinvDesc> &t, int Px, hipStream_t s, int var = 0);
+// local terms + Euler step (mode 1) or field output (mode 0) of many samples;
+// vec: every sample has nx % 4 == 0 (4 cells per thread); mapped: some
+// sample has an Ms map
+hipError_t launch_local_table(const Table<LocalDesc> &t, bool vec, bool mapped, const LocalParams &p,
+                              uint32_t terms, int mode, float dt, int renorm, int *flag, hipStream_t s);
+
+// Blocks of one sample's own grid (what its map entries count) for a pass
+// (0: x passes, 1: y passes, 2: z pass) with launch-shape variant var, and
+// for the local kernel (vec as above); local_perm: the XCD block order of
+// that sample's local grid (LocalDesc::perm_q).
+long long pass_blocks(int pass, const Geo &g, int var);
+long long local_blocks(const Geo &g, bool vec);
+int local_perm(const Geo &g, bool vec);
+// the variant a table launch of this pass and length actually uses
+int pass_variant(int pass, int L, int var);
 
 // Timing: events that the next launch of a timed kernel on this host thread
 // records itself at dispatch start and end.  launch_events_pending() tells

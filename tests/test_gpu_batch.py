@@ -135,3 +135,74 @@ def test_batch_launch_of_more_than_32_samples(gpu_lib):
         print(f"40-sample launches: worst member rel L2 vs single run {worst:.2e}")
         B.sync()
         B.close()
+
+
+def test_batch_launch_variants_and_autotune(gpu_lib, films, tmp_path):
+    """Launch-shape variants of the batched x and y launches regroup lines
+    only: after 20 steps with every x and y launch on variant 1, then 2, the
+    64 films equal the default run bit for bit (their z launches, 1 and 4
+    points, have no variants).  The autotuner's choice equals that of a
+    second, cached call, and a graph-replayed run with it equals the default
+    run too."""
+    import torch
+    w0 = films[0][0]
+    sizes = [w.n for (w, _, _) in films]
+    hs = [tuple(h) for (_, _, h) in films]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B = gpu_lib.Batch(sizes, w0.d, Ms=w0.Ms, A=w0.A, alpha=w0.alpha, hext=hs)
+        ref = B.pack([m0 for (_, m0, _) in films])
+        B.step(ref, 20, w0.dt)
+        n = len(B.tuning())
+        assert n >= 3
+        for v in (1, 2):
+            B.set_tuning([v] * n)
+            a = B.pack([m0 for (_, m0, _) in films])
+            B.step(a, 20, w0.dt)
+            s.synchronize()
+            assert torch.equal(a, ref), v
+        cache = str(tmp_path / "batch_tuning.txt")
+        ch = B.autotune(cache)
+        assert B.autotune(cache) == ch
+        print(f"64-film batch: {n} tunable launches, autotuned choice {ch}")
+        a = B.pack([m0 for (_, m0, _) in films])
+        B.step(a, 20, w0.dt, gpu_lib.MM_F_GRAPH)
+        s.synchronize()
+        assert torch.equal(a, ref)
+        B.sync()
+        B.close()
+
+
+def test_batch_z_variants_and_compensated_map(gpu_lib):
+    """Two cubes whose z launches have variants (64 and 128 points): with
+    every launch on variant 1 the plain step changes by rounding only
+    (1e-6), and the compensated step, which runs the z pass's default
+    shape whatever the tuning, equals the untuned compensated step bit for
+    bit (its block map covers both grids)."""
+    import torch
+    rng = np.random.default_rng(8)
+    sizes = [(32, 32, 32), (24, 20, 40)]
+    d = (5e-9, 5e-9, 5e-9)
+    kw = dict(Ms=8e5, A=1.3e-11, alpha=0.5)
+    m0s = [workloads.sphere(rng, (3, nz, ny, nx)) for (nx, ny, nz) in sizes]
+    B = gpu_lib.Batch(sizes, d, hext=[(1e4, 0.0, 0.0), (0.0, 2e4, 0.0)], **kw)
+    out = {}
+    for tuned in (False, True):
+        B.set_tuning([1 if tuned else 0] * len(B.tuning()))
+        for comp in (0, gpu_lib.MM_F_COMPENSATED):
+            m = B.pack(m0s)
+            B.step(m, 10, 1e-13, comp)
+            B.sync()
+            out[(tuned, comp)] = m.clone()
+    e = rel(host(out[(True, 0)]), host(out[(False, 0)]))
+    print(f"z variant 1 vs default, 2 cubes, 10 steps: rel L2 {e:.2e}")
+    assert 0 < e < 1e-6 or e == 0
+    assert torch.equal(out[(True, gpu_lib.MM_F_COMPENSATED)], out[(False, gpu_lib.MM_F_COMPENSATED)])
+    for i, (n, m0) in enumerate(zip(sizes, m0s)):
+        sim = gpu_lib.Sim(n, d, hext=[(1e4, 0.0, 0.0), (0.0, 2e4, 0.0)][i], **kw)
+        ms = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+        sim.step(ms, 10, 1e-13)
+        sim.sync()
+        assert rel(host(B.unpack(out[(False, 0)], i)), host(ms)) < 1e-6
+        sim.close()
+    B.close()
