@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel sources whose SHA-256 is
 # recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 680.4 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258098048,
-              "source_sha": "680b73a9938e9cb95f3bab067af735b7c91fdbc61d91a1fbb7e15e7a2c978089"},
+    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 680.5 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258098176,
+              "source_sha": "5521a3db72ad931afaa9269306989599e6917f0fe545f8d35e9e0bb7ffd82b72"},
 }
 
 def kernel_source_sha():
@@ -83,8 +83,9 @@ def calibration_copy(nbytes=1 << 30, reps=3):
 def kernel_bytes(n, P):
     """HBM bytes per launch of each kernel as implemented (FP32 data,
     complex64 spectra, each array read or written once; the tensor spectrum
-    is the real octant, 6 floats per stored frequency).  The x-inverse writes
-    H_demag and the local kernel reads it back."""
+    is the real octant, 6 floats per stored frequency).  Unfused, the
+    x-inverse writes H_demag and the local kernel reads it back; the fused
+    x-inverse + update reads S1 and m and writes m."""
     nx, ny, nz = n
     Px, Py, Pz = P
     Hx = Px // 2 + 1
@@ -96,7 +97,7 @@ def kernel_bytes(n, P):
     s2 = 8 * 3 * nz * Hx * Py
     k = 4 * 6 * Hx * Hy * Hz
     return {"xfwd": m + s1, "yfwd": s1 + s2, "zconv": 2 * s2 + k, "yinv": s2 + s1,
-            "xinv": s1 + m, "local": 3 * m}
+            "xinv": s1 + m, "local": 3 * m, "xinv_local": s1 + 2 * m}
 
 
 def model_bytes(n, P):
@@ -104,9 +105,28 @@ def model_bytes(n, P):
     and the local update counted as one pass (S1 read, m read, m written),
     i.e. without the H_demag round trip -- 734.15 MB at 256x256x32."""
     kb = kernel_bytes(n, P)
-    nx, ny, nz = n
-    m = 4 * 3 * nx * ny * nz
-    return kb["xfwd"] + kb["yfwd"] + kb["zconv"] + kb["yinv"] + (kb["xinv"] - m) + 2 * m
+    return kb["xfwd"] + kb["yfwd"] + kb["zconv"] + kb["yinv"] + kb["xinv_local"]
+
+
+def unfused_leg(binding, sim, m, w, flags, args):
+    """The same steps with the x-inverse and the update as two kernels
+    (H_demag written and read back): settle, time, then per-kernel events."""
+    import torch
+    binding.mm_set_fusion(sim.ctx, False)
+    sim.step(m, args.settle_steps + args.warmup, w.dt, flags)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(m, args.steps, w.dt, flags)
+    torch.cuda.synchronize()
+    us = 1e6 * (time.perf_counter() - t0) / max(args.steps, 1)
+    binding.mm_kernel_timing(sim.ctx, True)
+    sim.step(m, args.profile_steps, w.dt, flags)
+    times = binding.mm_kernel_times(sim.ctx)
+    binding.mm_kernel_timing(sim.ctx, False)
+    binding.mm_set_fusion(sim.ctx, True)
+    sim.sync()
+    return {"us_per_step": round(us, 2),
+            "kernels_us": {k: round(1e3 * tot / cnt, 2) for k, (tot, cnt) in times.items() if cnt}}
 
 
 def cpu_model():
@@ -498,6 +518,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--compensated", action="store_true",
                     help="run the headline timing with the compensated spectral multiply")
+    ap.add_argument("--no-fusion", action="store_true",
+                    help="run the headline timing with the x-inverse and the update as two kernels")
+    ap.add_argument("--no-unfused-leg", action="store_true",
+                    help="skip the timing of the two-kernel (unfused) step")
     ap.add_argument("--no-compensated-leg", action="store_true",
                     help="skip the plain-vs-compensated timing and crop errors")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
@@ -535,6 +559,7 @@ def main():
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t
     m = torch.tensor(m0, dtype=torch.float32, device=dev)
+    binding.mm_set_fusion(sim.ctx, not args.no_fusion)
 
     print(f"bench: {args.settle_steps} settle + {args.warmup} warm-up steps", file=sys.stderr, flush=True)
     sim.step(m, args.settle_steps, w.dt, flags)
@@ -570,8 +595,13 @@ def main():
                       "GBps": round(kb[k] / (avg_us * 1e-6) / 1e9, 1) if cnt else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     ach = kernels[dom]["GBps"]
-    step_bytes_impl = sum(kb.values())
+    step_bytes_impl = sum(kb[k] for k, v in kernels.items() if v["launches"])
     step_bytes = model_bytes(w.n, P)
+
+    unfused = None
+    if not args.no_unfused_leg and not args.no_fusion:
+        print("bench: unfused step (x-inverse and update as two kernels)", file=sys.stderr, flush=True)
+        unfused = unfused_leg(binding, sim, m, w, flags, args)
 
     sim.close()
     copy_bw = copy_bandwidth()
@@ -635,7 +665,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "block 256x256x32 cells, 5 nm cubes, padded FFT 512x512x64",
                    "cells": w.N, "dt": w.dt, "alpha": w.alpha, "Ms": w.Ms, "A": w.A,
-                   "spectral_multiply": "compensated" if args.compensated else "plain"},
+                   "spectral_multiply": "compensated" if args.compensated else "plain",
+                   "fused_xinv_update": not args.no_fusion},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)},
         "cpu_baseline": cpu,
@@ -643,6 +674,7 @@ def main():
         "step_bytes": step_bytes,
         "step_bytes_impl": step_bytes_impl,
         "step_hbm_frac_impl": round(step_bytes_impl / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+        "unfused": unfused,
         "compensated": comp,
         "copy_GBps": copy_bw,
         "step_hbm_frac": round(step_bytes / (ms_step * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),

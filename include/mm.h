@@ -233,6 +233,16 @@ mm_status mm_reduce_loss(mm_ctx *c, const float *m_dev, const float *target_dev,
 mm_status mm_reduce_loss_noalloc(mm_ctx *c, const float *m_dev, const float *target_dev, double *out_dev,
                                  float *grad_dev);
 
+/* Euler steps of mm_step_llg (and mm_forward_store, which stores H_demag, does
+ * not use it) run the x-inverse transform, the local terms and the update as
+ * one pass, so H_demag never goes to device memory (on != 0, the default),
+ * or as two passes (on = 0).  The fused pass applies to samples with a
+ * uniform Ms, nx a multiple of 4 and a padded x length of at most 512; other
+ * samples always take two.  Both give the same result bit for bit (the same
+ * transform and update arithmetic).  Sec. 3: the demag field, the local
+ * terms and the Euler step of eq. (3) per step. */
+mm_status mm_set_fusion(mm_ctx *c, int on);
+
 /* Use (on != 0) or stop using the compensated FP32 spectral multiply in every
  * demag evaluation of this context (mm_compute_heff, mm_reduce, steps and
  * adjoint steps), in addition to per-call MM_F_COMPENSATED. */
@@ -316,7 +326,8 @@ enum {
     MM_K_YINV = 3,   /* y-inverse FFT */
     MM_K_XINV = 4,   /* x-inverse real FFT -> H_demag */
     MM_K_LOCAL = 5,  /* local field terms (+ Euler LLG update in mm_step_llg) */
-    MM_K_COUNT = 6
+    MM_K_XINV_LOCAL = 6,  /* x-inverse + local terms + Euler update in one pass (mm_step_llg) */
+    MM_K_COUNT = 7
 };
 
 /* Diagnostic timing: while enabled, every kernel launched by mm_step_llg and

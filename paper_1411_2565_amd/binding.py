@@ -69,6 +69,7 @@ def load():
         "mm_sync": [_P],
         "mm_kernel_timing": [_P, ctypes.c_int],
         "mm_set_compensated": [_P, ctypes.c_int],
+        "mm_set_fusion": [_P, ctypes.c_int],
         "mm_set_tuning": [_P, ctypes.POINTER(ctypes.c_int32)],
         "mm_get_tuning": [_P, ctypes.POINTER(ctypes.c_int32)],
         "mm_autotune": [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)],
@@ -252,6 +253,10 @@ def mm_sync(ctx):
     _check(ctx, load().mm_sync(ctx), "mm_sync")
 
 
+def mm_set_fusion(ctx, on):
+    _check(ctx, load().mm_set_fusion(ctx, int(bool(on))), "mm_set_fusion")
+
+
 def mm_set_compensated(ctx, on):
     _check(ctx, load().mm_set_compensated(ctx, int(bool(on))), "mm_set_compensated")
 
@@ -308,7 +313,7 @@ def mm_adjoint_step(ctx, m_n, hd_n, lam, g_hext, g_ms, dt, flags, N):
            "mm_adjoint_step")
 
 
-MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local"]
+MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local", "xinv_local"]
 
 
 def mm_kernel_timing(ctx, enable):

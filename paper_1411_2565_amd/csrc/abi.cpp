@@ -54,6 +54,7 @@ struct mm_ctx {
     size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_rk = 0, o_T = 0, o_tA = 0, o_tB = 0;
     size_t o_ms = 0, o_h = 0, o_part = 0, o_lpart = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
+    bool fusion = true;        // Euler steps run the x-inverse and the update as one kernel where it applies
     bool vacuum = false;       // the Ms map holds vacuum cells (Ms = 0)
     int tune[3] = {0, 0, 0};   // launch-shape variants of the x, y and z passes
     // time-dependent external field: profile times, and which slot of the
@@ -286,13 +287,13 @@ mmk::LocalParams local_params(const mm_ctx *c)
 const float *ms_map_ptr(const mm_ctx *c) { return c->ms_map ? c->at<float>(c->o_ms) : nullptr; }
 const float *h_map_ptr(const mm_ctx *c) { return c->h_map ? c->at<float>(c->o_h) : nullptr; }
 
-// H_demag of m (M = Ms m, or M = m when unit_ms) into `out` or, if NULL, the
-// S2 region (aliased, 3N floats); *Hd receives the pointer
-mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd, float *out = nullptr, bool unit_ms = false)
+// The demag spectrum of m (M = Ms m, or M = m when unit_ms): the x-forward,
+// y-forward, z-convolution and y-inverse passes, leaving H_demag's x spectrum
+// in S1.
+mm_status demag_spectrum(mm_ctx *c, const float *m, bool comp, bool unit_ms = false)
 {
     const mmk::Geo &g = c->g;
     float2 *S1 = c->at<float2>(c->o_S1), *S2 = c->at<float2>(c->o_S2);
-    float *H = out ? out : c->at<float>(c->o_S2);
     const float *K = c->at<float>(c->o_K);
     hipStream_t s = c->stream;
     const float *msm = unit_ms ? nullptr : ms_map_ptr(c);
@@ -303,7 +304,17 @@ mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd, float *out = n
     MM_TRY(timed(c, MM_K_YFWD, "yfwd", [&] { return mmk::launch_yfwd(g, S1, S2, s, tv[1]); }));
     MM_TRY(timed(c, MM_K_ZCONV, "zconv", [&] { return mmk::launch_zconv(g, S2, K, comp, s, tv[2]); }));
     MM_TRY(timed(c, MM_K_YINV, "yinv", [&] { return mmk::launch_yinv(g, S2, S1, s, tv[1]); }));
-    MM_TRY(timed(c, MM_K_XINV, "xinv", [&] { return mmk::launch_xinv(g, S1, H, s, tv[0]); }));
+    return MM_OK;
+}
+
+// H_demag of m into `out` or, if NULL, the S2 region (aliased, 3N floats);
+// *Hd receives the pointer
+mm_status demag(mm_ctx *c, const float *m, bool comp, float **Hd, float *out = nullptr, bool unit_ms = false)
+{
+    MM_TRY(demag_spectrum(c, m, comp, unit_ms));
+    float *H = out ? out : c->at<float>(c->o_S2);
+    const float2 *S1 = c->at<float2>(c->o_S1);
+    MM_TRY(timed(c, MM_K_XINV, "xinv", [&] { return mmk::launch_xinv(c->g, S1, H, c->stream, c->tune[0]); }));
     *Hd = H;
     return MM_OK;
 }
@@ -608,9 +619,23 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
         return MM_OK;
     }
     p.dt64 = dt;
+    // the x-inverse and the update as one pass (H_demag stays on chip), unless
+    // H_demag is to be stored or an Ms map is set
+    const bool fuse = c->fusion && !c->ms_map && mmk::fused_xinv_euler_ok(c->g);
     for (int64_t s = 0; s < nsteps; ++s) {
+        float *hs = hd(s);
+        if (fuse && !hs) {
+            MM_TRY(demag_spectrum(c, src(s), comp));
+            p.tslot = c->tslot;
+            if (c->sched) c->tslot ^= 1;  // this step's kernel writes the next step's time
+            MM_TRY(timed(c, MM_K_XINV_LOCAL, "x-inverse + llg step", [&] {
+                return mmk::launch_xinv_euler(c->g, p, c->at<float2>(c->o_S1), src(s), h_map_ptr(c), (float)dt,
+                                              renorm, dst(s), flag, c->stream);
+            }));
+            continue;
+        }
         float *Hd = nullptr;
-        MM_TRY(demag(c, src(s), comp, &Hd, hd(s)));
+        MM_TRY(demag(c, src(s), comp, &Hd, hs));
         p.tslot = c->tslot;
         if (c->sched) c->tslot ^= 1;  // this step's kernel writes the next step's time
         MM_TRY(timed(c, MM_K_LOCAL, "llg step", [&] {
@@ -946,6 +971,14 @@ mm_status mm_autotune(mm_ctx *c, const char *cache_path, int32_t choice_out[3])
     c->drop_graphs();
     if (choice_out)
         for (int k = 0; k < 3; ++k) choice_out[k] = best[k];
+    return MM_OK;
+}
+
+mm_status mm_set_fusion(mm_ctx *c, int on)
+{
+    if (!c) return MM_EINVAL;
+    c->fusion = on != 0;
+    c->drop_graphs();
     return MM_OK;
 }
 

@@ -698,51 +698,28 @@ static int local_perm_q(const Geo &g, long long cells, long long nb)
     return (int)(P / 8);
 }
 
-// MAPPED: the samples carry an Ms map (per-cell Ms, and vacuum where it is 0);
-// without one the kernel compiles to the uniform-Ms code alone.
-template <int MODE, int V, bool TAB, bool MAPPED>
-__global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, LocalParams p, uint32_t terms,
-                                                    float dt, int renorm, int *__restrict__ flag)
+// Local field terms of V cells from cell i0 = (x0, y, z): loads m there into
+// mc (unless LOADED) and adds exchange, anisotropy and the (scaled) external field to h, which
+// holds H_demag (or zeros) on entry.  mag / inv_ms: magnetic cell, 1/Ms.
+// MAPPED: the sample carries an Ms map (per-cell Ms, and vacuum where it is
+// 0); without one this compiles to the uniform-Ms code alone.
+template <int V, bool MAPPED, bool LOADED = false>
+__device__ __forceinline__ void local_field(const LocalDesc &D, const LocalParams &p, uint32_t terms, float hsc,
+                                            long long i0, int x0, int y, int z, float (&mc)[3][V],
+                                            float (&h)[3][V], bool (&mag)[V], float (&inv_ms)[V])
 {
-    const long long lb = blockIdx.x;
-    const LocalDesc D = pass_desc(A);
     const Geo &g = D.g;
+    const long long N = g.N;
     const float *__restrict__ m = D.m;
-    const float *__restrict__ Hd = D.Hd;
     const float *__restrict__ ms_map = MAPPED ? D.ms_map : nullptr;
     const float *__restrict__ h_map = D.h_map;
-    float *__restrict__ out_m = D.m_out;
-    float *__restrict__ out_h = D.h_out;
-    // time-dependent field: every block reads this step's time from one
-    // clock slot; an Euler step writes the next step's time into the other
-    float hsc = 1.f;
-    if (p.sched) {
-        const double t = p.clk[p.tslot];
-        hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
-        if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
-    }
-    const long long i0 = ((long long)local_block((int)lb, D.perm_q) * kThreads + threadIdx.x) * V;
-    if (i0 >= g.N) return;
-    const long long N = g.N;
-    const int x0 = (int)(i0 % g.nx);
-    const long long r = i0 / g.nx;
-    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
-    float mc[3][V], h[3][V];
+    if constexpr (!LOADED) {  // else the caller has loaded m of these cells into mc
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        vload<V>(m + c * N + i0, mc[c]);
-        if ((terms & 2u) && Hd) {
-            vload<V>(Hd + c * N + i0, h[c]);
-        } else {
-#pragma unroll
-            for (int j = 0; j < V; ++j) h[c][j] = 0.f;
-        }
+        for (int c = 0; c < 3; ++c) vload<V>(m + c * N + i0, mc[c]);
     }
     // With an Ms map, cells with Ms = 0 are vacuum (non-regular geometry):
     // no exchange or anisotropy field there, exchange skips vacuum
     // neighbours (a free surface), and their state never moves.
-    float inv_ms[V];
-    bool mag[V];
     if constexpr (MAPPED) {
         float s[V];
         vload<V>(ms_map + i0, s);
@@ -856,6 +833,89 @@ __global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, L
             }
         }
     }
+}
+
+// Explicit Euler step of V cells with the field h (mode 1 of k_local): writes
+// P(m + dt f) to out_m, P the renormalisation unless renorm = 0; vacuum cells
+// keep their state.  Sets *flag on a non-finite result.
+template <int V>
+__device__ __forceinline__ void euler_store(const LocalParams &p, float dt, int renorm, const float (&mc)[3][V],
+                                            const float (&h)[3][V], const bool (&mag)[V], float *__restrict__ out_m,
+                                            long long N, long long i0, int *__restrict__ flag)
+{
+    float o[3][V];
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+        const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
+        if (!mag[j]) {  // vacuum: the state stays as it is
+            o[0][j] = mx;
+            o[1][j] = my;
+            o[2][j] = mz;
+            continue;
+        }
+        const float hx = h[0][j], hy = h[1][j], hz = h[2][j];
+        // m x H and m x (m x H)
+        const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
+        const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
+        float nx_ = mx + dt * (p.c1 * ax + p.c2 * bx);
+        float ny_ = my + dt * (p.c1 * ay + p.c2 * by);
+        float nz_ = mz + dt * (p.c1 * az + p.c2 * bz);
+        if (renorm) {
+            const float s = rsqrtf(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
+            nx_ *= s;
+            ny_ *= s;
+            nz_ *= s;
+        }
+        bad |= !(isfinite(nx_) && isfinite(ny_) && isfinite(nz_));
+        o[0][j] = nx_;
+        o[1][j] = ny_;
+        o[2][j] = nz_;
+    }
+    if (bad) *flag = 1;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vstore<V>(out_m + c * N + i0, o[c]);
+}
+
+// MAPPED: the samples carry an Ms map (per-cell Ms, and vacuum where it is 0);
+// without one the kernel compiles to the uniform-Ms code alone.
+template <int MODE, int V, bool TAB, bool MAPPED>
+__global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, LocalParams p, uint32_t terms,
+                                                    float dt, int renorm, int *__restrict__ flag)
+{
+    const long long lb = blockIdx.x;
+    const LocalDesc D = pass_desc(A);
+    const Geo &g = D.g;
+    const float *__restrict__ Hd = D.Hd;
+    float *__restrict__ out_m = D.m_out;
+    float *__restrict__ out_h = D.h_out;
+    // time-dependent field: every block reads this step's time from one
+    // clock slot; an Euler step writes the next step's time into the other
+    float hsc = 1.f;
+    if (p.sched) {
+        const double t = p.clk[p.tslot];
+        hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
+        if (MODE == 1 && blockIdx.x == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
+    }
+    const long long i0 = ((long long)local_block((int)lb, D.perm_q) * kThreads + threadIdx.x) * V;
+    if (i0 >= g.N) return;
+    const long long N = g.N;
+    const int x0 = (int)(i0 % g.nx);
+    const long long r = i0 / g.nx;
+    const int y = (int)(r % g.ny), z = (int)(r / g.ny);
+    float mc[3][V], h[3][V];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        if ((terms & 2u) && Hd) {
+            vload<V>(Hd + c * N + i0, h[c]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < V; ++j) h[c][j] = 0.f;
+        }
+    }
+    float inv_ms[V];
+    bool mag[V];
+    local_field<V, MAPPED>(D, p, terms, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
     if (MODE == 0) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) vstore<V>(out_h + c * N + i0, h[c]);
@@ -964,38 +1024,156 @@ __global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, L
         for (int c = 0; c < 3; ++c) vstore<V>(out_m + c * N + i0, o[c]);
         return;
     }
-    float o[3][V];
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-        const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
-        if (!mag[j]) {  // vacuum: the state stays as it is
-            o[0][j] = mx;
-            o[1][j] = my;
-            o[2][j] = mz;
-            continue;
-        }
-        const float hx = h[0][j], hy = h[1][j], hz = h[2][j];
-        // m x H and m x (m x H)
-        const float ax = my * hz - mz * hy, ay = mz * hx - mx * hz, az = mx * hy - my * hx;
-        const float bx = my * az - mz * ay, by = mz * ax - mx * az, bz = mx * ay - my * ax;
-        float nx_ = mx + dt * (p.c1 * ax + p.c2 * bx);
-        float ny_ = my + dt * (p.c1 * ay + p.c2 * by);
-        float nz_ = mz + dt * (p.c1 * az + p.c2 * bz);
-        if (renorm) {
-            const float s = rsqrtf(nx_ * nx_ + ny_ * ny_ + nz_ * nz_);
-            nx_ *= s;
-            ny_ *= s;
-            nz_ *= s;
-        }
-        bad |= !(isfinite(nx_) && isfinite(ny_) && isfinite(nz_));
-        o[0][j] = nx_;
-        o[1][j] = ny_;
-        o[2][j] = nz_;
+    euler_store<V>(p, dt, renorm, mc, h, mag, out_m, N, i0, flag);
+}
+
+// ------------------------------------------------------------------------
+// a5-a8 in one pass: the x-inverse real FFT of the three components of LPB
+// y-lines of one z-plane (H_demag of those cells, which never goes to HBM),
+// then the local terms and the explicit Euler step of the same cells.
+//   Transforms: 3 LPB lines of L = Px/2 complex points, T = L/E threads per
+//   line as in the x-inverse pass; each line lies within one wavefront.  The
+//   S1 tile of every component is read in runs of LPB consecutive y.
+//   Update: H_demag goes to LDS as [3][LPB][nx] floats and the first
+//   LPB nx/4 threads take 4 consecutive cells each (nx % 4 == 0).  Those
+//   threads issue the loads of m at their own cells together with the S1
+//   tile, so that they complete under the transform (measured: 26.4 us
+//   against 28.0 us with the loads after it, 256x256x32 block; tiles of 4 or
+//   2 y-lines, 29.3 and 33.2 us).
+// Block order: G = 16/LPB tiles share the 128-byte lines of S1 (runs of LPB
+// complex values).  Block b = 8 G K + 8 h + x (x the XCD) takes tile G P + h
+// of the tile group P = 8 K + x, so the tiles of a group run back to back on
+// one XCD, and each XCD keeps the same y-tiles in every z-plane (the
+// z-neighbour rows of its cells stay in its L2).
+// ------------------------------------------------------------------------
+#ifndef MMK_XE_LPB
+#define MMK_XE_LPB 8
+#endif
+
+template <int L, int LPB_>
+struct XEShape {
+    static constexpr int E = elems_per_thread(L), T = L / E;
+    static constexpr int LPB = LPB_;     // y-lines per component
+    static constexpr int G = 16 / LPB;   // tiles per 128-byte S1 line
+    static constexpr int NL = 3 * LPB;   // lines per block
+    static constexpr int THREADS = NL * T;
+    static constexpr int LD = lds_line(L);
+    static constexpr int LDS = NL * LD + L + 1;  // line buffers + unpack twiddles (complex)
+    // H_demag of the block's cells ([3][LPB][nx] floats, nx <= L) fits in the line buffers
+    static_assert(3 * LPB * L <= 2 * NL * LD, "H_demag tile exceeds the line buffers");
+    // one thread per 4 cells of the LPB rows of nx <= L cells
+    static_assert(LPB * L / 4 <= THREADS, "too few threads for the update");
+};
+
+template <int L, int LPB_>
+__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(XinvDesc DX, LocalDesc DL,
+                                                                           LocalParams p, float dt, int renorm,
+                                                                           int *__restrict__ flag)
+{
+    using S = XEShape<L, LPB_>;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB, NL = S::NL, LD = S::LD, G = S::G;
+    extern __shared__ float2 sm[];
+    const Geo &g = DX.g;
+    const float2 *__restrict__ S1 = DX.S1;
+    float hsc = 1.f;
+    if (p.sched) {  // time-dependent field, as in k_local's Euler step
+        const double t = p.clk[p.tslot];
+        hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
+        if (blockIdx.x == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
     }
-    if (bad) *flag = 1;
+    const int ntiles = (g.ny + LPB - 1) / LPB;
+    int z, tile;
+    {
+        const int b = blockIdx.x, groups = ntiles / G;
+        if (ntiles % G == 0 && ((long long)g.nz * groups) % 8 == 0) {
+            const int P = 8 * (b / (8 * G)) + (b & 7);
+            z = P / groups;
+            tile = G * (P - z * groups) + (b / 8) % G;
+        } else {
+            z = b / ntiles;
+            tile = b - z * ntiles;
+        }
+    }
+    const int y0 = tile * LPB;
+    const int nl = min(LPB, g.ny - y0);
+    // this thread's update cells: 4 from (x0, y, z), if it has any
+    const int q4 = g.nx / 4;
+    const int w = threadIdx.x;
+    const int yl_u = w / q4, x0 = (w - yl_u * q4) * 4, y = y0 + yl_u;
+    const bool upd = w < LPB * q4 && y < g.ny;
+    const long long i0 = ((long long)z * g.ny + y) * g.nx + x0;
+    float2 *const tw = sm + NL * LD;
+    load_half_twiddles<L, S::THREADS>(tw);
+    // the three components' tiles, (L + 1) x NL entries, line r = c LPB + yl
+    constexpr int NIT = ((L + 1) * NL + S::THREADS - 1) / S::THREADS;
+    float2 tile_v[NIT];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vstore<V>(out_m + c * N + i0, o[c]);
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * S::THREADS;
+        const int kx = idx / NL, r = idx - kx * NL;
+        const int c = r / LPB, yl = r - c * LPB;
+        tile_v[it] = (idx < (L + 1) * NL && yl < nl)
+                         ? S1[(((long long)c * g.nz + z) * g.Hx + kx) * g.ny + y0 + yl]
+                         : make_float2(0.f, 0.f);
+    }
+    float mc[3][4];
+    if (upd) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) vload<4>(DL.m + c * g.N + i0, mc[c]);
+    }
+    const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
+    TwSet<L, E> twl;
+    load_twiddles<L, E>(twl, t);
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int idx = threadIdx.x + it * S::THREADS;
+        const int kx = idx / NL, r = idx - kx * NL;
+        if (idx < (L + 1) * NL) sm[r * LD + kx] = tile_v[it];
+    }
+    __syncthreads();
+    float2 v[1][E];
+    {
+        const float2 *X = sm + ll * LD;
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int k = t + q * T;
+            const float2 xk = X[k], xc = cconj(X[L - k]);
+            const float2 Ev = cadd(xk, xc);
+            const float2 Od = cmul(csub(xk, xc), cconj(tw[k]));
+            v[0][q] = cadd(Ev, mul_mi<true>(Od));
+        }
+    }
+    __syncthreads();
+    float2 *const lds[1] = {sm + ll * LD};
+    reg_fft<L, true, MMK_WAVE_FFT && (T <= 64)>(v, lds, t, twl);
+    __syncthreads();  // every line is done with its buffer before H_demag overwrites them
+    float *const sH = reinterpret_cast<float *>(sm);
+    {
+        const int c = ll / LPB, yl = ll - c * LPB;
+        if (yl < nl) {
+            float *row = sH + (c * LPB + yl) * g.nx;
+#pragma unroll
+            for (int q = 0; q < half_elems(E); ++q) {
+                const int xx = 2 * (t + q * T);
+                if (xx < g.nx) *reinterpret_cast<float2 *>(row + xx) = v[0][q];
+            }
+        }
+    }
+    __syncthreads();
+    if (!upd) return;  // no barrier follows
+    float h[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float4 hv = *reinterpret_cast<const float4 *>(sH + (c * LPB + yl_u) * g.nx + x0);
+        h[c][0] = hv.x;
+        h[c][1] = hv.y;
+        h[c][2] = hv.z;
+        h[c][3] = hv.w;
+    }
+    bool mag[4];
+    float inv_ms[4];
+    local_field<4, false, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
+    euler_store<4>(p, dt, renorm, mc, h, mag, DL.m_out, g.N, i0, flag);
 }
 
 // ------------------------------------------------------------------------
@@ -1846,6 +2024,37 @@ hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, cons
 {
     LocalDesc d{g, m, Hd, ms_map, h_map, out_m, nullptr, p.h0, p.h1, p.h2, m_base, acc, eacc, kbuf};
     return launch_local_one(d, p, 15u, 2, dt, renorm, flag, s);
+}
+
+bool fused_xinv_euler_ok(const Geo &g)
+{
+    const int L = g.Px / 2;
+    return g.nx % 4 == 0 && L >= 4 && L <= 256 && g.nx <= L;
+}
+
+hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
+                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s)
+{
+    if (!fused_xinv_euler_ok(g)) return hipErrorInvalidValue;
+    const XinvDesc dx{g, S1, nullptr};
+    LocalDesc dl{g, m, nullptr, nullptr, h_map, out_m, nullptr, p.h0, p.h1, p.h2};
+    switch (g.Px / 2) {
+#define CASE(LL)                                                                              \
+    case LL: {                                                                                \
+        if constexpr (LL >= 4 && LL <= 256) {                                                 \
+            using S = XEShape<LL, MMK_XE_LPB>;                                                \
+            const unsigned nb = (unsigned)g.nz * ((g.ny + S::LPB - 1) / S::LPB);              \
+            MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB>), dim3(nb), dim3(S::THREADS),    \
+                       S::LDS * sizeof(float2), s, dx, dl, p, dt, renorm, flag);              \
+        }                                                                                     \
+        break;                                                                                \
+    }
+        MM_LEN_CASES(CASE)
+#undef CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // Maximum of n non-negative floats (NaN propagates): grid-stride loop, LDS

@@ -174,6 +174,12 @@ hipError_t launch_xinv(const Geo &g, const float2 *S1, float *Hd, hipStream_t s,
 hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, const float *Hd,
                         const float *ms_map, const float *h_map, uint32_t terms, int mode,
                         float dt, int renorm, float *out_m, float *out_h, int *flag, hipStream_t s);
+// a5-a8 in one launch: x-inverse of S1 (H_demag kept on chip) + local terms +
+// Euler step of m into out_m; for uniform Ms, nx % 4 == 0 and Px <= 512
+// (fused_xinv_euler_ok)
+bool fused_xinv_euler_ok(const Geo &g);
+hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
+                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s);
 // one Runge-Kutta stage (all field terms; coefficients in p.stage_*): reads
 // m (the stage state), Hd = H_demag(m), m_base and acc; writes out_m and acc
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,

@@ -28,19 +28,22 @@ def test_padded_sizes():
 
 def test_byte_model_of_the_block_step():
     """Per-pass algorithmic bytes of the 256x256x32 step (complex64 spectra,
-    FP32 state, real octant tensor): the survey's a1-a4 figures and its
-    734.15 MB total, plus the separate x-inverse pass (75.7 MB) that the
-    five-pass pipeline adds over a fused a5-a8."""
+    FP32 state, real octant tensor): the a1-a4 figures and the 734.15 MB
+    total of the fused step, and the 784.5 MB of the step with the
+    x-inverse and the update as two kernels (H_demag written and read
+    back)."""
     kb = bench.kernel_bytes((256, 256, 32), (512, 512, 64))
     mb = {k: v / 1e6 for k, v in kb.items()}
     assert abs(mb["xfwd"] - 75.7) < 0.1
     assert abs(mb["yfwd"] - 151.6) < 0.1
     assert abs(mb["zconv"] - 254.4) < 0.1
     assert abs(mb["yinv"] - 151.6) < 0.1
-    assert abs(sum(mb.values()) - 784.48) < 0.1
-    # the fused a5-a8 tail would not write H_demag and read it back: 2 x 25.17 MB
+    assert abs(mb["xinv_local"] - 100.86) < 0.01
+    unfused = ("xfwd", "yfwd", "zconv", "yinv", "xinv", "local")
+    assert abs(sum(mb[k] for k in unfused) - 784.48) < 0.1
+    # the fused tail does not write H_demag and read it back: 2 x 25.17 MB
     h_round_trip = 2 * 4 * 3 * 256 * 256 * 32
-    assert abs((sum(kb.values()) - h_round_trip) / 1e6 - 734.15) < 0.1
+    assert abs(kb["xinv"] + kb["local"] - h_round_trip - kb["xinv_local"]) == 0
     # the headline fraction of HBM peak is taken on that 734.15 MB model
     assert abs(bench.model_bytes((256, 256, 32), (512, 512, 64)) / 1e6 - 734.15) < 0.1
 

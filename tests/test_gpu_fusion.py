@@ -1,0 +1,119 @@
+"""The fused x-inverse + update pass against the two-kernel step, through the
+C ABI.
+
+Euler steps run the x-inverse transform, the local terms and the update as
+one pass by default (H_demag stays on chip); with the fusion switched off
+they run as the x-inverse kernel (H_demag to device memory) and the update
+kernel.  Both evaluate the same transform and the same update arithmetic, so
+every state after n steps must agree bit for bit: ragged y tiles, z-planes
+whose tile count is odd, every x transform length up to 256, anisotropy, a
+uniform and a mapped external field, the time-dependent field and graph
+replays.  Samples the fused pass does not cover (nx not a multiple of 4)
+take the two kernels either way.
+
+Paper: Zhu, arXiv:1411.2565, Sec. 3 (demag field, local terms, Euler step
+of eq. (3)).
+"""
+import numpy as np
+import pytest
+
+from paper_1411_2565_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
+
+
+def run(gpu_lib, n, steps, fused, hmap=None, sched=None, flags=0, seed=5):
+    rng = np.random.default_rng(seed)
+    sim = gpu_lib.Sim(n, (4e-9, 5e-9, 3e-9), Ms=8.0e5, A=1.3e-11, Ku=5e4, u=(0.6, 0.0, 0.8), alpha=0.3,
+                      hext=(2e4, -1e4, 3e4))
+    gpu_lib.mm_set_fusion(sim.ctx, fused)
+    hm = None  # the context keeps the map's pointer: hold the tensor until the end
+    if hmap is not None:
+        hm = gpu(hmap)
+        gpu_lib.mm_set_hext_map(sim.ctx, hm, sim.N)
+    if sched is not None:
+        sim.set_field_schedule(sched)
+        sim.set_time(0.0)
+    m = gpu(workloads.sphere(rng, (3, n[2], n[1], n[0])))
+    sim.step(m, steps, 2e-14, flags)
+    sim.sync()
+    t = sim.time() if sched is not None else None
+    times = None
+    gpu_lib.mm_kernel_timing(sim.ctx, True)
+    sim.step(m, 1, 2e-14, flags)
+    times = gpu_lib.mm_kernel_times(sim.ctx)
+    gpu_lib.mm_kernel_timing(sim.ctx, False)
+    sim.sync()
+    sim.close()
+    del hm
+    return m, t, times
+
+
+# (nx, ny, nz): x transform lengths 4..256, ragged y tiles (ny % 8 != 0),
+# odd tile counts and z-plane counts that break the paired block order
+SIZES = [(4, 3, 2), (8, 8, 1), (16, 16, 2), (20, 12, 3), (32, 32, 4), (64, 24, 5), (100, 9, 2),
+         (128, 128, 4), (256, 40, 3), (256, 256, 32)]
+
+
+@pytest.mark.parametrize("n", SIZES, ids=lambda n: "x".join(map(str, n)))
+def test_fused_step_equals_two_kernel_step(gpu_lib, n):
+    import torch
+    steps = 3 if n == (256, 256, 32) else 7
+    a, _, ta = run(gpu_lib, n, steps, True)
+    b, _, tb = run(gpu_lib, n, steps, False)
+    assert torch.isfinite(a).all()
+    assert torch.equal(a, b), f"{n}: max |diff| {(a - b).abs().max().item():.3e}"
+    # the fused pass really ran (one launch per step) and the unfused did not
+    assert ta["xinv_local"][1] == 1 and ta["xinv"][1] == 0 and ta["local"][1] == 0
+    assert tb["xinv_local"][1] == 0 and tb["xinv"][1] == 1 and tb["local"][1] == 1
+
+
+def test_unfusable_sample_takes_two_kernels(gpu_lib):
+    import torch
+    n = (18, 10, 2)  # nx % 4 != 0
+    a, _, ta = run(gpu_lib, n, 5, True)
+    b, _, _ = run(gpu_lib, n, 5, False)
+    assert torch.equal(a, b)
+    assert ta["xinv_local"][1] == 0 and ta["xinv"][1] == 1 and ta["local"][1] == 1
+
+
+@pytest.mark.parametrize("n", [(32, 20, 3), (128, 64, 4)], ids=lambda n: "x".join(map(str, n)))
+def test_fused_step_with_field_map_and_schedule(gpu_lib, n):
+    import torch
+    rng = np.random.default_rng(8)
+    hmap = 4e4 * rng.standard_normal((3, n[2], n[1], n[0]))
+    sched = (3e-14, 9e-14, 1.5e-13)  # on after 2 steps, decays from step 5, off after step 8
+    a, ta, _ = run(gpu_lib, n, 10, True, hmap=hmap, sched=sched)
+    b, tb, _ = run(gpu_lib, n, 10, False, hmap=hmap, sched=sched)
+    assert torch.equal(a, b)
+    assert ta == tb and abs(ta - 10 * 2e-14) < 1e-25
+
+
+def test_fused_graph_replays_equal_eager_two_kernel_steps(gpu_lib):
+    """Graph replays (capture needs a stream of its own) of fused steps,
+    three replays with eager work and a synchronisation between them, each
+    equal to the eager two-kernel steps."""
+    import torch
+    n = (64, 48, 4)
+    rng = np.random.default_rng(9)
+    m0 = workloads.sphere(rng, (3, n[2], n[1], n[0]))
+    s = torch.cuda.Stream()
+    kw = dict(Ms=8.0e5, A=1.3e-11, Ku=5e4, alpha=0.3, hext=(2e4, 0.0, 1e4))
+    with torch.cuda.stream(s):
+        fused = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # fused steps in one captured graph
+        split = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # eager two-kernel steps
+        gpu_lib.mm_set_fusion(split.ctx, False)
+        graph, eager = gpu(m0), gpu(m0)
+        for rep in range(3):
+            fused.step(graph, 20, 2e-14, gpu_lib.MM_F_GRAPH)
+            split.step(eager, 20, 2e-14)
+            fused.sync()
+            split.sync()
+            assert torch.equal(graph, eager), rep
+        fused.close()
+        split.close()
