@@ -81,6 +81,23 @@ constexpr int kThreads = 256;
 #endif
 // x passes and y-inverse: FFT stages ordered within each wavefront instead of
 // by block barriers (every line of these passes lies within one wavefront)
+#ifndef MMK_ZC_SEQ_MIN
+#define MMK_ZC_SEQ_MIN 256
+#endif
+#ifndef MMK_ZC_SEQ_CB
+#define MMK_ZC_SEQ_CB 8
+#endif
+#ifndef MMK_ZC_SEQ_WAVES
+#define MMK_ZC_SEQ_WAVES 3
+#endif
+#if MMK_ZC_SEQ_WAVES > 0
+#define MMK_ZC_SEQ_ATTR __attribute__((amdgpu_waves_per_eu(MMK_ZC_SEQ_WAVES)))
+#else
+#define MMK_ZC_SEQ_ATTR
+#endif
+#ifndef MMK_ZC_SEQ_THREADS
+#define MMK_ZC_SEQ_THREADS 256
+#endif
 #ifndef MMK_WAVE_FFT
 #define MMK_WAVE_FFT 1
 #endif
@@ -134,23 +151,37 @@ struct YShape {
     static constexpr int LDS = LPB * lds_line(L);
 };
 // z pass: CB columns of the three components per block; V = 1: the other
-// point count per thread (4 <-> 8), V = 2: half the columns
+// point count per thread (4 <-> 8), V = 2: half the columns.
+// Transforms of MMK_ZC_SEQ_MIN points and more: V = 0 is the SEQ form
+// (k_zconv_seq), where the three components of a column are transformed one
+// after another through one exchange buffer per column, in blocks of
+// MMK_ZC_SEQ_THREADS threads (CB = 8 columns of 256 points, 4 of 512; the
+// G = 16/CB tiles of a 128-byte S2 row run as blocks 8 apart, on one XCD);
+// V = 2 is then the concurrent form with the default columns (16 of 256
+// points, 8 of 512 with two tiles per block).
 template <int L, int V = 0>
 struct ZShape {
+    static constexpr bool LONG = L >= MMK_ZC_SEQ_MIN;
+    static constexpr bool SEQ = LONG && V == 0;
     static constexpr int Ed = L >= 256 ? MMK_ZC_E_LONG : MMK_ZC_E;
     static constexpr int E0 = V == 1 ? (Ed == 4 ? 8 : 4) : Ed;
     static constexpr int E = L < E0 ? L : E0, T = L / E;
     static constexpr int KB = L >= 128 ? MMK_ZC_LDS_KB_LONG : MMK_ZC_LDS_KB;
-    static constexpr int CBmax = cmax(1, (KB * 1024) / (3 * 8 * lds_line(L)));
+    static constexpr int BUFS = SEQ ? 1 : 3;  // exchange buffers per column
+    static constexpr int CBmax = cmax(1, (KB * 1024) / (BUFS * 8 * lds_line(L)));
     static constexpr int CB0 = cmin(cmin(cmax(1, 1024 / T), pow2floor(CBmax)), L >= 128 ? MMK_ZC_CB_LONG : 1024);
-    static constexpr int CB = V == 2 ? cmax(1, CB0 / 2) : CB0;
-    // Long transforms whose LDS budget leaves fewer than 16 columns per
-    // pass: one block takes NSUB adjacent tiles of CB columns in turn, so the
-    // 128-byte rows of S2 that the tiles share are read by one block, back
-    // to back, instead of by blocks on different XCDs.
-    static constexpr int NSUB = (L >= 128 && CB < 16) ? 16 / CB : 1;
+    static constexpr int CB = SEQ ? cmin(cmin(CB0, MMK_ZC_SEQ_CB), cmax(1, MMK_ZC_SEQ_THREADS / T))
+                                  : ((V == 2 && !LONG) ? cmax(1, CB0 / 2) : CB0);
+    // Long concurrent transforms whose LDS budget leaves fewer than 16
+    // columns per pass: one block takes NSUB adjacent tiles of CB columns in
+    // turn, so the 128-byte rows of S2 that the tiles share are read by one
+    // block, back to back, instead of by blocks on different XCDs.  SEQ
+    // blocks of fewer than 16 columns take one tile, and the G = 16/CB tiles
+    // of a row run as blocks dispatched back to back on one XCD.
+    static constexpr int NSUB = (!SEQ && L >= 128 && CB < 16) ? 16 / CB : 1;
+    static constexpr int G = (SEQ && CB < 16) ? 16 / CB : 1;
     static constexpr int THREADS = T * CB;
-    static constexpr int LDS = nstages(L, E) > 1 ? 3 * CB * lds_line(L) : 1;
+    static constexpr int LDS = nstages(L, E) > 1 ? BUFS * CB * lds_line(L) : 1;
 };
 // x passes: LPB lines of L = Px/2 complex per block (16 for 128-byte runs
 // in the transposed layout); V = 1 / 2: 8 / 32 lines
@@ -453,10 +484,43 @@ __device__ __forceinline__ int zc_tile(int slot, int ntiles)
     return r < 8 ? lower : ntiles - 1 - lower;
 }
 
+// H(k) = K(k) M(k) at one frequency kz of a column: the octant entries
+// K[kx][kyf][kzf] (6 floats: xx yy zz xy xz yz) with the signs of the
+// mirrored axes (N_xy odd in ky, N_xz in kz, N_yz in both).  ok = false (a
+// column beyond Py) multiplies by zero.
+template <bool COMP>
+__device__ __forceinline__ void zc_point(float2 &mx, float2 &my, float2 &mz, const float *kcol, bool ok, int kz,
+                                         int Pz, float sy)
+{
+    const bool fz = kz > Pz / 2;
+    const int kzf = fz ? Pz - kz : kz;
+    const float sz = fz ? -1.f : 1.f;
+    float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
+    if (ok) {
+        const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
+        k01 = kp[0];
+        k23 = kp[1];
+        k45 = kp[2];
+    }
+    const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
+    const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
+    const float2 ax = mx, ay = my, az = mz;
+    if (COMP) {
+        mx = make_float2(dot3_comp(kxx, ax.x, kxy, ay.x, kxz, az.x), dot3_comp(kxx, ax.y, kxy, ay.y, kxz, az.y));
+        my = make_float2(dot3_comp(kxy, ax.x, kyy, ay.x, kyz, az.x), dot3_comp(kxy, ax.y, kyy, ay.y, kyz, az.y));
+        mz = make_float2(dot3_comp(kxz, ax.x, kyz, ay.x, kzz, az.x), dot3_comp(kxz, ax.y, kyz, ay.y, kzz, az.y));
+    } else {
+        mx = make_float2(fmaf(kxx, ax.x, fmaf(kxy, ay.x, kxz * az.x)), fmaf(kxx, ax.y, fmaf(kxy, ay.y, kxz * az.y)));
+        my = make_float2(fmaf(kxy, ax.x, fmaf(kyy, ay.x, kyz * az.x)), fmaf(kxy, ax.y, fmaf(kyy, ay.y, kyz * az.y)));
+        mz = make_float2(fmaf(kxz, ax.x, fmaf(kyz, ay.x, kzz * az.x)), fmaf(kxz, ax.y, fmaf(kyz, ay.y, kzz * az.y)));
+    }
+}
+
 template <int L, bool COMP, int V, bool TAB>
 __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc, TAB> A)
 {
     using S = ZShape<L, V>;
+    static_assert(!S::SEQ, "SEQ shapes run k_zconv_seq");
     constexpr int E = S::E, T = S::T, CB = S::CB;
     constexpr int NSUB = S::NSUB;
     extern __shared__ float2 sm[];
@@ -500,7 +564,7 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc
         // one twiddle set for both transforms, loaded while the data arrive
         TwSet<L, E> tw;
         load_twiddles<L, E>(tw, t);
-        const int hy = g.Py / 2, hz = g.Pz / 2;
+        const int hy = g.Py / 2;
         const bool fy = ky > hy;
         const int kyf = fy ? g.Py - ky : ky;
         const float sy = fy ? -1.f : 1.f;
@@ -510,31 +574,7 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc
                                 sm + (2 * CB + col) * lds_line(L)};
         reg_fft<L, false>(v, lds, t, tw);
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
-            const int kz = t + q * T;
-            const bool fz = kz > hz;
-            const int kzf = fz ? g.Pz - kz : kz;
-            const float sz = fz ? -1.f : 1.f;
-            float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
-            if (ok) {
-                const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
-                k01 = kp[0];
-                k23 = kp[1];
-                k45 = kp[2];
-            }
-            const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
-            const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
-            const float2 mx = v[0][q], my = v[1][q], mz = v[2][q];
-            if (COMP) {
-                v[0][q] = make_float2(dot3_comp(kxx, mx.x, kxy, my.x, kxz, mz.x), dot3_comp(kxx, mx.y, kxy, my.y, kxz, mz.y));
-                v[1][q] = make_float2(dot3_comp(kxy, mx.x, kyy, my.x, kyz, mz.x), dot3_comp(kxy, mx.y, kyy, my.y, kyz, mz.y));
-                v[2][q] = make_float2(dot3_comp(kxz, mx.x, kyz, my.x, kzz, mz.x), dot3_comp(kxz, mx.y, kyz, my.y, kzz, mz.y));
-            } else {
-                v[0][q] = make_float2(fmaf(kxx, mx.x, fmaf(kxy, my.x, kxz * mz.x)), fmaf(kxx, mx.y, fmaf(kxy, my.y, kxz * mz.y)));
-                v[1][q] = make_float2(fmaf(kxy, mx.x, fmaf(kyy, my.x, kyz * mz.x)), fmaf(kxy, mx.y, fmaf(kyy, my.y, kyz * mz.y)));
-                v[2][q] = make_float2(fmaf(kxz, mx.x, fmaf(kyz, my.x, kzz * mz.x)), fmaf(kxz, mx.y, fmaf(kyz, my.y, kzz * mz.y)));
-            }
-        }
+        for (int q = 0; q < E; ++q) zc_point<COMP>(v[0][q], v[1][q], v[2][q], kcol, ok, t + q * T, g.Pz, sy);
         reg_fft<L, true>(v, lds, t, tw);
         if (ok) {
 #pragma unroll
@@ -544,6 +584,98 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc
                     const int zz = t + q * T;
                     if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
                 }
+        }
+    }
+}
+
+// SEQ blocks of G > 1 tiles per 128-byte row: the G tiles of row group j
+// and the G tiles of its mirror group go to blocks 8 apart from each other
+// (one XCD, dispatched back to back), lower tiles first.  A bijection on
+// [0, ntiles) when ntiles is a multiple of 16 G; else zc_tile's order.
+__device__ __forceinline__ int zc_tile_seq(int slot, int ntiles, int G)
+{
+    const int span = 2 * G;
+    if (G < 2 || ntiles % (8 * span) != 0) return zc_tile(slot, ntiles);
+    const int grp = slot / (8 * span), r = slot - grp * 8 * span;
+    const int which = r >> 3, j = grp * 8 + (r & 7);
+    return which < G ? j * G + which : ntiles - 1 - (j * G + (span - 1 - which));
+}
+
+// The z pass for long transforms (ZShape::SEQ): the same arithmetic as
+// k_zconv, with the three components of a column transformed in turn through
+// the column's one exchange buffer (each transform's last exchange ends with
+// a barrier after its reads, so the next one's first writes cannot overtake
+// them).  Each component is stored as soon as its inverse transform ends.
+// Blocks of MMK_ZC_SEQ_THREADS threads held to MMK_ZC_SEQ_WAVES waves per
+// SIMD: the form needs 164-173 VGPRs, and at 256^3 (512-point columns) 3
+// waves per SIMD (168 VGPRs, 3 spilled) ran the pass in 767 us against 910
+// us at 2; 4 waves spill 60-90 registers.
+template <int L, bool COMP, int V, bool TAB>
+__global__ __launch_bounds__((ZShape<L, V>::THREADS)) MMK_ZC_SEQ_ATTR void k_zconv_seq(PassArg<ZDesc, TAB> A)
+{
+    using S = ZShape<L, V>;
+    static_assert(S::SEQ && S::NSUB == 1, "sequential-component form");
+    constexpr int E = S::E, T = S::T, CB = S::CB, H = half_elems(E);
+    extern __shared__ float2 sm[];
+    const ZDesc D = pass_desc(A);
+    const Geo &g = D.g;
+    int slot, kx, nst;
+    if constexpr (TAB) {
+        nst = (g.Py + CB - 1) / CB;
+        slot = (int)(blockIdx.x % nst);
+        kx = (int)(blockIdx.x / nst);
+    } else {
+        slot = blockIdx.x;
+        kx = blockIdx.y;
+        nst = gridDim.x;
+    }
+    const int t = threadIdx.x / CB, col = threadIdx.x - t * CB;
+    const int tile = S::G > 1 ? zc_tile_seq(slot, nst, S::G) : zc_tile(slot, nst);
+    if (kx >= g.Hx || tile * CB >= g.Py) return;  // block-uniform, before any barrier
+    const int ky = tile * CB + col;
+    const bool ok = ky < g.Py;
+    const long long zs = g.Py;                           // stride between z
+    const long long cs = (long long)g.Hx * g.nz * g.Py;  // between components
+    float2 *__restrict__ base = D.S2 + (long long)kx * g.nz * g.Py + ky;
+    float2 v[3][E];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int zz = t + q * T;
+            v[c][q] = (q < H && ok && zz < g.nz) ? base[c * cs + zz * zs] : make_float2(0.f, 0.f);
+        }
+    TwSet<L, E> tw;
+    load_twiddles<L, E>(tw, t);
+    // Each transform takes its thread index and buffer offset from an empty
+    // asm statement: the three transforms address the same LDS slots, and
+    // without this the compiler kept their common addresses in registers
+    // from the first transform to the last.
+    auto fft = [&](auto inv, int c) {
+        int tt = t, off = col * lds_line(L);
+        asm volatile("" : "+v"(tt), "+v"(off));
+        float2 *const l1[1] = {sm + off};
+        reg_fft<L, decltype(inv)::value>(*reinterpret_cast<float2(*)[1][E]>(&v[c][0]), l1, tt, tw);
+    };
+#pragma unroll
+    for (int c = 0; c < 3; ++c) fft(std::false_type{}, c);
+    const bool fy = ky > g.Py / 2;
+    const int kyf = fy ? g.Py - ky : ky;
+    const float sy = fy ? -1.f : 1.f;
+    const float *kcol = D.K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
+#pragma unroll
+    for (int q = 0; q < E; ++q) zc_point<COMP>(v[0][q], v[1][q], v[2][q], kcol, ok, t + q * T, g.Pz, sy);
+    // store addresses computed afresh rather than kept from the loads
+    asm volatile("" : "+v"(base));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        fft(std::true_type{}, c);
+        if (ok) {
+#pragma unroll
+            for (int q = 0; q < H; ++q) {
+                const int zz = t + q * T;
+                if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
+            }
         }
     }
 }
@@ -1655,6 +1787,19 @@ static void with_variant(int var, F &&go)
     go(std::integral_constant<int, 0>{});
 }
 
+// One z launch: the sequential-component kernel for SEQ shapes, else the
+// concurrent one.
+template <int LL, int VV, bool COMP, bool TAB>
+static void zc_launch(dim3 grid, const PassArg<ZDesc, TAB> &a, hipStream_t s)
+{
+    using S = ZShape<LL, VV>;
+    const size_t lds = S::LDS * sizeof(float2);
+    if constexpr (S::SEQ)
+        MMK_LAUNCH((k_zconv_seq<LL, COMP, VV, TAB>), grid, dim3(S::THREADS), lds, s, a);
+    else
+        MMK_LAUNCH((k_zconv<LL, COMP, VV, TAB>), grid, dim3(S::THREADS), lds, s, a);
+}
+
 int pass_variant(int pass, int L, int var)
 {
     (void)pass;
@@ -1816,13 +1961,11 @@ hipError_t launch_zconv(const Geo &g, float2 *S2, const float *K, bool comp, hip
             constexpr int VV = decltype(vt)::value;                                           \
             using S = ZShape<LL, VV>;                                                         \
             constexpr int CT = S::CB * S::NSUB;                                               \
-            dim3 grid((g.Py + CT - 1) / CT, g.Hx);                                            \
-            const size_t lds = S::LDS * sizeof(float2);                                       \
+            const dim3 grid((g.Py + CT - 1) / CT, g.Hx);                                      \
             if (comp) {                                                                       \
-                if constexpr (VV == 0)                                                        \
-                    MMK_LAUNCH((k_zconv<LL, true, 0, false>), grid, dim3(S::THREADS), lds, s, a); \
+                if constexpr (VV == 0) zc_launch<LL, 0, true, false>(grid, a, s);             \
             } else {                                                                          \
-                MMK_LAUNCH((k_zconv<LL, false, VV, false>), grid, dim3(S::THREADS), lds, s, a); \
+                zc_launch<LL, VV, false, false>(grid, a, s);                                  \
             }                                                                                 \
         });                                                                                   \
         break;                                                                                \
@@ -1947,15 +2090,10 @@ hipError_t launch_zconv_table(const Table<ZDesc> &t, int Pz, bool comp, hipStrea
     case LL: {                                                                                \
         with_variant<LL>(comp ? 0 : var, [&](auto vt) {                                       \
             constexpr int VV = decltype(vt)::value;                                           \
-            using S = ZShape<LL, VV>;                                                         \
-            const size_t lds = S::LDS * sizeof(float2);                                       \
             if (comp) {                                                                       \
-                if constexpr (VV == 0)                                                        \
-                    MMK_LAUNCH((k_zconv<LL, true, 0, true>), tgrid(t),       \
-                               dim3(S::THREADS), lds, s, a);                                  \
+                if constexpr (VV == 0) zc_launch<LL, 0, true, true>(tgrid(t), a, s);          \
             } else {                                                                          \
-                MMK_LAUNCH((k_zconv<LL, false, VV, true>), tgrid(t),         \
-                           dim3(S::THREADS), lds, s, a);                                      \
+                zc_launch<LL, VV, false, true>(tgrid(t), a, s);                               \
             }                                                                                 \
         });                                                                                   \
         break;                                                                                \
