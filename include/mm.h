@@ -237,7 +237,7 @@ mm_status mm_reduce_loss_noalloc(mm_ctx *c, const float *m_dev, const float *tar
  * not use it) run the x-inverse transform, the local terms and the update as
  * one pass, so H_demag never goes to device memory (on != 0, the default),
  * or as two passes (on = 0).  The fused pass applies to samples with a
- * uniform Ms, nx a multiple of 4 and a padded x length of at most 512; other
+ * uniform Ms and a padded x length Px with 8 <= Px <= 512 (nx >= 3); other
  * samples always take two.  Both give the same result bit for bit (the same
  * transform and update arithmetic).  Sec. 3: the demag field, the local
  * terms and the Euler step of eq. (3) per step. */
@@ -378,6 +378,16 @@ mm_status mm_batch_build_tensor(mm_batch *b);
 /* nsteps Euler steps of every sample, in place in the packed state; flags
  * as mm_step_llg (MM_F_GRAPH captures chunks of 32 steps of the whole batch) */
 mm_status mm_batch_step(mm_batch *b, float *m_packed, int64_t nsteps, double dt, uint32_t flags);
+/* As mm_set_fusion, for the batch's Euler steps: with on != 0 and every
+ * sample having a fused form (8 <= Px <= 512), each group of samples with
+ * one padded x length and one update width (nx % 4 == 0 or not) runs the
+ * x-inverse, the local terms and the update as one launch; else (on = 0,
+ * the default) the x-inverse and update launches.  Same results bit for
+ * bit.  Off by default: batches of thin films give the fused launch too few
+ * blocks per sample to overlap its phases (64 films of 1-2 layers: 192 us
+ * per step fused against 176 us).  Drops the batch's captured graphs.
+ * Sec. 3, applied to every sample. */
+mm_status mm_batch_set_fusion(mm_batch *b, int on);
 /* Launch-shape tuning of the batch's launches (the paper leaves FFT
  * performance to its FFT library, Sec. 3): one choice in
  * [0, MM_TUNE_VARIANTS) per x, y and z launch, in that order and, within a

@@ -70,6 +70,7 @@ def load():
         "mm_kernel_timing": [_P, ctypes.c_int],
         "mm_set_compensated": [_P, ctypes.c_int],
         "mm_set_fusion": [_P, ctypes.c_int],
+        "mm_batch_set_fusion": [_P, ctypes.c_int],
         "mm_set_tuning": [_P, ctypes.POINTER(ctypes.c_int32)],
         "mm_get_tuning": [_P, ctypes.POINTER(ctypes.c_int32)],
         "mm_autotune": [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)],
@@ -401,6 +402,10 @@ def mm_batch_get_tuning(b):
     return tuple(arr[:n.value])
 
 
+def mm_batch_set_fusion(b, on):
+    _bcheck(b, load().mm_batch_set_fusion(b, int(bool(on))), "mm_batch_set_fusion")
+
+
 def mm_batch_set_tuning(b, choices):
     arr = (ctypes.c_int32 * max(len(choices), 1))(*[int(v) for v in choices])
     _bcheck(b, load().mm_batch_set_tuning(b, arr, len(choices)), "mm_batch_set_tuning")
@@ -464,6 +469,9 @@ class Batch:
 
     def set_tuning(self, choices):
         mm_batch_set_tuning(self.b, choices)
+
+    def set_fusion(self, on):
+        mm_batch_set_fusion(self.b, on)
 
     def tuning(self):
         return mm_batch_get_tuning(self.b)

@@ -1206,8 +1206,8 @@ struct mm_batch {
     };
     // one launch of a pass: samples with one transform length
     struct Launch {
-        int pass = 0;                   // 0 x, 1 y, 2 z, 3 local
-        int len = 0;                    // Px, Py, Pz; local: 1 if nx % 4 == 0
+        int pass = 0;                   // 0 x, 1 y, 2 z, 3 local, 4 fused x-inverse + update
+        int len = 0;                    // Px, Py, Pz; local: 1 if nx % 4 == 0; fused: 2 Px + (nx % 4 == 0)
         int var = 0;                    // launch-shape variant
         std::vector<int> members;
         long long width = 0;            // blocks per sample in the grid (current variant)
@@ -1215,7 +1215,9 @@ struct mm_batch {
     };
     std::vector<Sample> samples;
     std::vector<Group> groups;
-    std::vector<Launch> launches;       // x, then y, then z, then local
+    std::vector<Launch> launches;       // x, then y, then z, then local, then fused
+    bool fusion = false;      // Euler steps run the fused x-inverse + update launches (off: slower for thin films)
+    bool all_fusable = false; // every sample has a fused form
     size_t total_state = 0;  // floats in the packed state
     size_t o_flag = 0, o_plan = 0, plan_bytes = 0, total = 0;
     char *ws = nullptr;
@@ -1304,6 +1306,7 @@ const float *spectrum_of(const mm_batch *b, int i) { return b->at<float>(b->grou
 long long sample_blocks(const mm_batch *b, const mm_batch::Launch &L, int i, int v)
 {
     const mmk::Geo &g = b->samples[i].g;
+    if (L.pass == 4) return mmk::xe_blocks(g);
     if (L.pass == 3) return mmk::local_blocks(g, L.len != 0);
     if (L.pass == 2) return std::max(mmk::pass_blocks(2, g, v), mmk::pass_blocks(2, g, 0));
     return mmk::pass_blocks(L.pass, g, v);
@@ -1320,11 +1323,15 @@ void plan_launches(mm_batch *b)
 {
     b->launches.clear();
     const int ns = (int)b->samples.size();
-    for (int pass = 0; pass < 4; ++pass) {
+    b->all_fusable = true;
+    for (const auto &sm : b->samples) b->all_fusable = b->all_fusable && mmk::fused_xinv_euler_ok(sm.g);
+    for (int pass = 0; pass < 5; ++pass) {
+        if (pass == 4 && !b->all_fusable) break;
         std::vector<std::pair<int, int>> keyed;
         for (int i = 0; i < ns; ++i) {
             const mmk::Geo &g = b->samples[i].g;
-            const int key = pass == 0 ? g.Px : pass == 1 ? g.Py : pass == 2 ? g.Pz : (g.nx % 4 == 0 ? 1 : 0);
+            const int vec = g.nx % 4 == 0 ? 1 : 0;
+            const int key = pass == 0 ? g.Px : pass == 1 ? g.Py : pass == 2 ? g.Pz : pass == 3 ? vec : 2 * g.Px + vec;
             keyed.push_back({key, i});
         }
         std::stable_sort(keyed.begin(), keyed.end(), [](const auto &u, const auto &v) { return u.first < v.first; });
@@ -1358,6 +1365,10 @@ size_t plan_layout(mm_batch *b, size_t base)
             break;
         case 2:
             L.o_desc[0] = cv.take(sizeof(mmk::ZDesc) * n);
+            break;
+        case 4:  // fused x-inverse + update, even and odd steps
+            L.o_desc[0] = cv.take(sizeof(mmk::XeDesc) * n);
+            L.o_desc[1] = cv.take(sizeof(mmk::XeDesc) * n);
             break;
         default:  // local, even and odd steps
             L.o_desc[0] = cv.take(sizeof(mmk::LocalDesc) * n);
@@ -1396,6 +1407,10 @@ std::vector<char> plan_image(const mm_batch *b, const float *m)
                         const mmk::ZDesc zd{sm.g, b->at<float2>(sm.o_S2), spectrum_of(b, L.members[k])};
                         put(L.o_desc[0] + sizeof(zd) * k, &zd, sizeof(zd));
                     }
+                } else if (L.pass == 4) {
+                    const mmk::XeDesc xe{sm.g, b->at<float2>(sm.o_S1), src, nullptr, dst,
+                                         (float)sm.h[0], (float)sm.h[1], (float)sm.h[2], 0};
+                    put(L.o_desc[par] + sizeof(xe) * k, &xe, sizeof(xe));
                 } else {
                     mmk::LocalDesc ld{sm.g, src, b->at<float>(sm.o_S2), nullptr, nullptr, dst, nullptr,
                                       (float)sm.h[0], (float)sm.h[1], (float)sm.h[2]};
@@ -1436,6 +1451,7 @@ mm_status batch_enqueue(mm_batch *b, int64_t nsteps, double dt, uint32_t flags)
     const int renorm = (flags & MM_F_NO_RENORM) ? 0 : 1;
     int *flag = b->at<int>(b->o_flag);
     hipStream_t st = b->stream;
+    const bool fuse = b->fusion && b->all_fusable;
     for (int64_t s = 0; s < nsteps; ++s) {
         const int par = (int)(s & 1);
         for (const auto &L : b->launches)
@@ -1451,6 +1467,14 @@ mm_status batch_enqueue(mm_batch *b, int64_t nsteps, double dt, uint32_t flags)
         for (const auto &L : b->launches)
             if (L.pass == 1)
                 MM_TRY(bhip(b, mmk::launch_yinv_table(table_of<mmk::YDesc>(b, L, 1), L.len, st, L.var), "batch yinv"));
+        if (fuse) {
+            for (const auto &L : b->launches)
+                if (L.pass == 4)
+                    MM_TRY(bhip(b, mmk::launch_xinv_euler_table(table_of<mmk::XeDesc>(b, L, par), L.len / 2,
+                                                                (L.len & 1) != 0, p, (float)dt, renorm, flag, st),
+                                "batch x-inverse + update"));
+            continue;
+        }
         for (const auto &L : b->launches)
             if (L.pass == 0)
                 MM_TRY(bhip(b, mmk::launch_xinv_table(table_of<mmk::XinvDesc>(b, L, 2), L.len, st, L.var), "batch xinv"));
@@ -1494,7 +1518,7 @@ uint64_t batch_key(const mm_batch *b)
 int tunable_launches(const mm_batch *b)
 {
     int n = 0;
-    for (const auto &L : b->launches) n += L.pass < 3;
+    for (const auto &L : b->launches) n += L.pass < 3;  // x, y and z
     return n;
 }
 
@@ -1734,6 +1758,14 @@ mm_status mm_batch_step(mm_batch *b, float *m, int64_t nsteps, double dt, uint32
     return ((nsteps - done) & 1) ? batch_copy_back(b, m) : MM_OK;
 }
 
+mm_status mm_batch_set_fusion(mm_batch *b, int on)
+{
+    if (!b) return MM_EINVAL;
+    b->fusion = on != 0;
+    b->drop_graphs();
+    return MM_OK;
+}
+
 mm_status mm_batch_set_tuning(mm_batch *b, const int32_t *choices, int32_t n)
 {
     if (!b) return MM_EINVAL;
@@ -1744,7 +1776,7 @@ mm_status mm_batch_set_tuning(mm_batch *b, const int32_t *choices, int32_t n)
             return bfail(b, MM_EINVAL, "tuning choice %d out of range [0, %d)", choices[k], MM_TUNE_VARIANTS);
     int k = 0;
     for (auto &L : b->launches) {
-        if (L.pass == 3) continue;
+        if (L.pass >= 3) continue;
         const int L1 = L.pass == 0 ? L.len / 2 : L.len;
         L.var = mmk::pass_variant(L.pass, L1, choices[k++]);
         L.width = launch_width(b, L, L.var);
@@ -1827,7 +1859,7 @@ mm_status mm_batch_autotune(mm_batch *b, const char *cache_path, int32_t *choice
         mm_status status = MM_OK;
         int k = 0;
         for (auto &L : b->launches) {
-            if (L.pass == 3 || status != MM_OK) continue;
+            if (L.pass >= 3 || status != MM_OK) continue;
             const int L1 = L.pass == 0 ? L.len / 2 : L.len;
             float best_t = 0.f;
             for (int v = 0; v < MM_TUNE_VARIANTS && status == MM_OK; ++v) {

@@ -1166,12 +1166,15 @@ __global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, L
 //   Transforms: 3 LPB lines of L = Px/2 complex points, T = L/E threads per
 //   line as in the x-inverse pass; each line lies within one wavefront.  The
 //   S1 tile of every component is read in runs of LPB consecutive y.
-//   Update: H_demag goes to LDS as [3][LPB][nx] floats and the first
-//   LPB nx/4 threads take 4 consecutive cells each (nx % 4 == 0).  Those
-//   threads issue the loads of m at their own cells together with the S1
-//   tile, so that they complete under the transform (measured: 26.4 us
-//   against 28.0 us with the loads after it, 256x256x32 block; tiles of 4 or
-//   2 y-lines, 29.3 and 33.2 us).
+//   Update: H_demag goes to LDS as [3][LPB][nx] floats.  V = 4 (nx % 4 ==
+//   0): the first LPB nx/4 threads take 4 consecutive cells each and issue
+//   the loads of m at their cells together with the S1 tile, so that they
+//   complete under the transform (measured: 26.4 us against 28.0 us with
+//   the loads after it, 256x256x32 block; tiles of 4 or 2 y-lines, 29.3 and
+//   33.2 us).  V = 1: the threads take the tile's cells one at a time.
+//   Both use k_local's device functions, so the result equals the two-kernel
+//   step bit for bit.
+// TAB: many samples, one per blockIdx.y (descriptors in device memory).
 // Block order: G = 16/LPB tiles share the 128-byte lines of S1 (runs of LPB
 // complex values).  Block b = 8 G K + 8 h + x (x the XCD) takes tile G P + h
 // of the tile group P = 8 K + x, so the tiles of a group run back to back on
@@ -1197,23 +1200,27 @@ struct XEShape {
     static_assert(LPB * L / 4 <= THREADS, "too few threads for the update");
 };
 
-template <int L, int LPB_>
-__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(XinvDesc DX, LocalDesc DL,
-                                                                           LocalParams p, float dt, int renorm,
+template <int L, int LPB_, int V, bool TAB>
+__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(PassArg<XeDesc, TAB> A, LocalParams p,
+                                                                           float dt, int renorm,
                                                                            int *__restrict__ flag)
 {
     using S = XEShape<L, LPB_>;
     constexpr int E = S::E, T = S::T, LPB = S::LPB, NL = S::NL, LD = S::LD, G = S::G;
     extern __shared__ float2 sm[];
-    const Geo &g = DX.g;
-    const float2 *__restrict__ S1 = DX.S1;
+    const XeDesc D = pass_desc(A);
+    const Geo &g = D.g;
+    const float2 *__restrict__ S1 = D.S1;
     float hsc = 1.f;
     if (p.sched) {  // time-dependent field, as in k_local's Euler step
         const double t = p.clk[p.tslot];
         hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
-        if (blockIdx.x == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
     }
     const int ntiles = (g.ny + LPB - 1) / LPB;
+    if constexpr (TAB) {
+        if ((long long)blockIdx.x >= (long long)g.nz * ntiles) return;  // block-uniform, before any barrier
+    }
     int z, tile;
     {
         const int b = blockIdx.x, groups = ntiles / G;
@@ -1226,13 +1233,14 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Xinv
             tile = b - z * ntiles;
         }
     }
+    const LocalDesc DL{g, D.m, nullptr, nullptr, D.h_map, D.m_out, nullptr, D.h0, D.h1, D.h2};
     const int y0 = tile * LPB;
     const int nl = min(LPB, g.ny - y0);
-    // this thread's update cells: 4 from (x0, y, z), if it has any
+    // V = 4: this thread's update cells, 4 from (x0, y, z), if it has any
     const int q4 = g.nx / 4;
     const int w = threadIdx.x;
-    const int yl_u = w / q4, x0 = (w - yl_u * q4) * 4, y = y0 + yl_u;
-    const bool upd = w < LPB * q4 && y < g.ny;
+    const int yl_u = V == 4 ? w / q4 : 0, x0 = V == 4 ? (w - yl_u * q4) * 4 : 0, y = y0 + yl_u;
+    const bool upd = V == 4 && w < LPB * q4 && y < g.ny;
     const long long i0 = ((long long)z * g.ny + y) * g.nx + x0;
     float2 *const tw = sm + NL * LD;
     load_half_twiddles<L, S::THREADS>(tw);
@@ -1251,7 +1259,7 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Xinv
     float mc[3][4];
     if (upd) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) vload<4>(DL.m + c * g.N + i0, mc[c]);
+        for (int c = 0; c < 3; ++c) vload<4>(D.m + c * g.N + i0, mc[c]);
     }
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
     TwSet<L, E> twl;
@@ -1284,28 +1292,50 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Xinv
         const int c = ll / LPB, yl = ll - c * LPB;
         if (yl < nl) {
             float *row = sH + (c * LPB + yl) * g.nx;
+            const bool even = (g.nx & 1) == 0;
 #pragma unroll
             for (int q = 0; q < half_elems(E); ++q) {
                 const int xx = 2 * (t + q * T);
-                if (xx < g.nx) *reinterpret_cast<float2 *>(row + xx) = v[0][q];
+                if (xx < g.nx) {
+                    if (even) {
+                        *reinterpret_cast<float2 *>(row + xx) = v[0][q];
+                    } else {
+                        row[xx] = v[0][q].x;
+                        if (xx + 1 < g.nx) row[xx + 1] = v[0][q].y;
+                    }
+                }
             }
         }
     }
     __syncthreads();
-    if (!upd) return;  // no barrier follows
-    float h[3][4];
+    if constexpr (V == 4) {
+        if (!upd) return;  // no barrier follows
+        float h[3][4];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        const float4 hv = *reinterpret_cast<const float4 *>(sH + (c * LPB + yl_u) * g.nx + x0);
-        h[c][0] = hv.x;
-        h[c][1] = hv.y;
-        h[c][2] = hv.z;
-        h[c][3] = hv.w;
+        for (int c = 0; c < 3; ++c) {
+            const float4 hv = *reinterpret_cast<const float4 *>(sH + (c * LPB + yl_u) * g.nx + x0);
+            h[c][0] = hv.x;
+            h[c][1] = hv.y;
+            h[c][2] = hv.z;
+            h[c][3] = hv.w;
+        }
+        bool mag[4];
+        float inv_ms[4];
+        local_field<4, false, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
+        euler_store<4>(p, dt, renorm, mc, h, mag, D.m_out, g.N, i0, flag);
+    } else {
+        for (int wi = threadIdx.x; wi < nl * g.nx; wi += S::THREADS) {
+            const int yl = wi / g.nx, x = wi - yl * g.nx;
+            const long long i = ((long long)z * g.ny + y0 + yl) * g.nx + x;
+            float m1[3][1], h1[3][1];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h1[c][0] = sH[(c * LPB + yl) * g.nx + x];
+            bool mag[1];
+            float inv_ms[1];
+            local_field<1, false>(DL, p, 15u, hsc, i, x, y0 + yl, z, m1, h1, mag, inv_ms);
+            euler_store<1>(p, dt, renorm, m1, h1, mag, D.m_out, g.N, i, flag);
+        }
     }
-    bool mag[4];
-    float inv_ms[4];
-    local_field<4, false, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
-    euler_store<4>(p, dt, renorm, mc, h, mag, DL.m_out, g.N, i0, flag);
 }
 
 // ------------------------------------------------------------------------
@@ -1467,13 +1497,44 @@ __global__ __launch_bounds__(kThreads) void k_adj_b(Geo g, LocalParams p, const 
 // ------------------------------------------------------------------------
 constexpr int kEq = 8;  // e_ex, e_d, e_an, e_z, sum mx, sum my, sum mz, magnetic cells
 
+// NV values reduced over the kThreads threads of a block by an associative
+// op: shuffles within each wavefront, then the wavefronts' results in order
+// by thread 0 (a fixed order, so sums are deterministic).  The result is
+// valid in thread 0; lds holds kThreads / 64 * NV values.
+template <int NV, typename T, typename Op>
+__device__ __forceinline__ void block_reduce(T (&v)[NV], T *lds, Op op)
+{
+#pragma unroll
+    for (int q = 0; q < NV; ++q)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[q] = op(v[q], __shfl_down(v[q], off, 64));
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) lds[(threadIdx.x >> 6) * NV + q] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+            T r = lds[q];
+            for (int w = 1; w < kThreads / 64; ++w) r = op(r, lds[w * NV + q]);
+            v[q] = r;
+        }
+    }
+}
+
+struct OpAdd {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a + b; }
+};
+
 __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, const float *__restrict__ m,
                                                      const float *__restrict__ Hd,
                                                      const float *__restrict__ ms_map,
                                                      const float *__restrict__ h_map,
                                                      double *__restrict__ partials)
 {
-    __shared__ double red[kEq][kThreads];
+    __shared__ double red[kThreads / 64 * kEq];
     double acc[kEq] = {0, 0, 0, 0, 0, 0, 0, 0};
     const long long N = g.N;
     // the external field at the clock's time, scaled as in the step (FP32
@@ -1516,52 +1577,37 @@ __global__ __launch_bounds__(kThreads) void k_energy(Geo g, EnergyParams p, cons
         acc[6] += mz;
         acc[7] += 1.0;
     }
+    block_reduce<kEq>(acc, red, OpAdd{});
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int q = 0; q < kEq; ++q) red[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int q = 0; q < kEq; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        }
-        __syncthreads();
+        for (int q = 0; q < kEq; ++q) partials[(long long)blockIdx.x * kEq + q] = acc[q];
     }
-    if (threadIdx.x < kEq) partials[(long long)blockIdx.x * kEq + threadIdx.x] = red[threadIdx.x][0];
 }
 
 __global__ __launch_bounds__(kThreads) void k_energy_final(int nblk, EnergyParams p, long long N,
                                                            const double *__restrict__ partials,
                                                            double *__restrict__ out)
 {
-    __shared__ double red[kEq][kThreads];
+    __shared__ double red[kThreads / 64 * kEq];
     double acc[kEq] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int b = threadIdx.x; b < nblk; b += kThreads)
 #pragma unroll
         for (int q = 0; q < kEq; ++q) acc[q] += partials[(long long)b * kEq + q];
-#pragma unroll
-    for (int q = 0; q < kEq; ++q) red[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int q = 0; q < kEq; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
+    block_reduce<kEq>(acc, red, OpAdd{});
     if (threadIdx.x == 0) {
-        const double eex = (p.terms & 1u) ? p.A * p.V * red[0][0] : 0.0;
-        const double ed = (p.terms & 2u) ? -0.5 * p.mu0 * p.V * red[1][0] : 0.0;
-        const double ean = (p.terms & 4u) ? p.Ku * p.V * red[2][0] : 0.0;
-        const double ez = (p.terms & 8u) ? -p.mu0 * p.V * red[3][0] : 0.0;
+        const double eex = (p.terms & 1u) ? p.A * p.V * acc[0] : 0.0;
+        const double ed = (p.terms & 2u) ? -0.5 * p.mu0 * p.V * acc[1] : 0.0;
+        const double ean = (p.terms & 4u) ? p.Ku * p.V * acc[2] : 0.0;
+        const double ez = (p.terms & 8u) ? -p.mu0 * p.V * acc[3] : 0.0;
         out[0] = eex;
         out[1] = ed;
         out[2] = ean;
         out[3] = ez;
         out[4] = eex + ed + ean + ez;
-        const double cells = red[7][0];  // magnetic cells (all N without vacuum)
-        out[5] = cells > 0.0 ? red[4][0] / cells : 0.0;
-        out[6] = cells > 0.0 ? red[5][0] / cells : 0.0;
-        out[7] = cells > 0.0 ? red[6][0] / cells : 0.0;
+        const double cells = acc[7];  // magnetic cells (all N without vacuum)
+        out[5] = cells > 0.0 ? acc[4] / cells : 0.0;
+        out[6] = cells > 0.0 ? acc[5] / cells : 0.0;
+        out[7] = cells > 0.0 ? acc[6] / cells : 0.0;
     }
 }
 
@@ -2167,52 +2213,78 @@ hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, cons
 bool fused_xinv_euler_ok(const Geo &g)
 {
     const int L = g.Px / 2;
-    return g.nx % 4 == 0 && L >= 4 && L <= 256 && g.nx <= L;
+    return L >= 4 && L <= 256 && g.nx <= L;
 }
 
-hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
-                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s)
+long long xe_blocks(const Geo &g)
 {
-    if (!fused_xinv_euler_ok(g)) return hipErrorInvalidValue;
-    const XinvDesc dx{g, S1, nullptr};
-    LocalDesc dl{g, m, nullptr, nullptr, h_map, out_m, nullptr, p.h0, p.h1, p.h2};
-    switch (g.Px / 2) {
+    return (long long)g.nz * ((g.ny + MMK_XE_LPB - 1) / MMK_XE_LPB);
+}
+
+template <bool TAB>
+static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px, bool vec, const LocalParams &p,
+                                float dt, int renorm, int *flag, hipStream_t s)
+{
+    switch (Px / 2) {
 #define CASE(LL)                                                                              \
     case LL: {                                                                                \
         if constexpr (LL >= 4 && LL <= 256) {                                                 \
             using S = XEShape<LL, MMK_XE_LPB>;                                                \
-            const unsigned nb = (unsigned)g.nz * ((g.ny + S::LPB - 1) / S::LPB);              \
-            MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB>), dim3(nb), dim3(S::THREADS),    \
-                       S::LDS * sizeof(float2), s, dx, dl, p, dt, renorm, flag);              \
+            const size_t lds = S::LDS * sizeof(float2);                                       \
+            if (vec)                                                                          \
+                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 4, TAB>), grid, dim3(S::THREADS), lds, s, a, p, dt, \
+                           renorm, flag);                                                     \
+            else                                                                              \
+                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 1, TAB>), grid, dim3(S::THREADS), lds, s, a, p, dt, \
+                           renorm, flag);                                                     \
+            return hipGetLastError();                                                         \
         }                                                                                     \
         break;                                                                                \
     }
         MM_LEN_CASES(CASE)
 #undef CASE
     default:
-        return hipErrorInvalidValue;
+        break;
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-// Maximum of n non-negative floats (NaN propagates): grid-stride loop, LDS
-// tree per block, one atomicMax on the bit pattern per block.
+hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
+                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s)
+{
+    if (!fused_xinv_euler_ok(g)) return hipErrorInvalidValue;
+    const PassArg<XeDesc, false> a{XeDesc{g, S1, m, h_map, out_m, p.h0, p.h1, p.h2, 0}};
+    return launch_xe_any(a, dim3((unsigned)xe_blocks(g)), g.Px, g.nx % 4 == 0, p, dt, renorm, flag, s);
+}
+
+hipError_t launch_xinv_euler_table(const Table<XeDesc> &t, int Px, bool vec, const LocalParams &p, float dt,
+                                   int renorm, int *flag, hipStream_t s)
+{
+    if (!table_ok(t)) return hipErrorInvalidValue;
+    return launch_xe_any(targ(t), tgrid(t), Px, vec, p, dt, renorm, flag, s);
+}
+
+struct OpMax {
+    __device__ unsigned operator()(unsigned a, unsigned b) const { return a > b ? a : b; }
+};
+struct OpOr {
+    __device__ unsigned operator()(unsigned a, unsigned b) const { return a | b; }
+};
+
+// Maximum of n non-negative floats (NaN propagates): grid-stride loop,
+// wavefront shuffles and the wavefronts' results per block, one atomicMax on
+// the bit pattern per block.
 __global__ __launch_bounds__(kThreads) void k_errmax(const float *__restrict__ e, long long n,
                                                      unsigned *__restrict__ out)
 {
-    __shared__ unsigned red[kThreads];
-    unsigned mx = 0u;
+    __shared__ unsigned red[kThreads / 64];
+    unsigned mx[1] = {0u};
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
         const unsigned v = __float_as_uint(e[i]);
-        mx = v > mx ? v : mx;
+        mx[0] = v > mx[0] ? v : mx[0];
     }
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(out, red[0]);
+    block_reduce<1>(mx, red, OpMax{});
+    if (threadIdx.x == 0) atomicMax(out, mx[0]);
 }
 
 // Checks an Ms map: out[0] |= 1 if some value is negative, NaN or infinite
@@ -2221,26 +2293,17 @@ __global__ __launch_bounds__(kThreads) void k_errmax(const float *__restrict__ e
 __global__ __launch_bounds__(kThreads) void k_map_check(const float *__restrict__ v, long long n,
                                                         unsigned *__restrict__ out)
 {
-    __shared__ unsigned red[2][kThreads];
-    unsigned bad = 0u, zero = 0u;
+    __shared__ unsigned red[kThreads / 64 * 2];
+    unsigned f[2] = {0u, 0u};  // bad, zero
     for (long long i = (long long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long long)gridDim.x * kThreads) {
         const unsigned b = __float_as_uint(v[i]);
-        bad |= b > 0x7f7fffffu ? 1u : 0u;
-        zero |= b == 0u ? 1u : 0u;
+        f[0] |= b > 0x7f7fffffu ? 1u : 0u;
+        f[1] |= b == 0u ? 1u : 0u;
     }
-    red[0][threadIdx.x] = bad;
-    red[1][threadIdx.x] = zero;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[0][threadIdx.x] |= red[0][threadIdx.x + w];
-            red[1][threadIdx.x] |= red[1][threadIdx.x + w];
-        }
-        __syncthreads();
-    }
+    block_reduce<2>(f, red, OpOr{});
     if (threadIdx.x == 0) {
-        if (red[0][0]) atomicOr(out, 1u);
-        if (red[1][0]) atomicOr(out + 1, 1u);
+        if (f[0]) atomicOr(out, 1u);
+        if (f[1]) atomicOr(out + 1, 1u);
     }
 }
 
@@ -2356,13 +2419,9 @@ static_assert(kLossChunk % kThreads == 0, "loss chunk is whole rows of the block
 
 __device__ __forceinline__ double block_sum256(double v, double *lds)
 {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kThreads / 64; ++w) r += lds[w];
-    return r;  // valid in thread 0
+    double r[1] = {v};
+    block_reduce<1>(r, lds, OpAdd{});
+    return r[0];  // valid in thread 0
 }
 
 __global__ __launch_bounds__(kThreads) void k_loss(const float *__restrict__ m, const float *__restrict__ t,

@@ -77,6 +77,16 @@ struct LocalDesc {
     float *kbuf;          // mode 2: stored slopes k_0, k_1, ... (3N floats each) for tableaus with full rows
     int perm_q;           // set by the launcher: blocks per XCD per z-plane of the block order (0: launch order)
 };
+// The fused x-inverse + Euler update of one sample: H_demag's x spectrum S1
+// in, the state m read, the next state m_out written.
+struct XeDesc {
+    Geo g;
+    const float2 *S1;
+    const float *m, *h_map;
+    float *m_out;
+    float h0, h1, h2;  // uniform external field of this sample (no map)
+    int pad;
+};
 // Where a pass kernel finds its sample and its block within the sample.
 //   TAB = false: one sample, its descriptor by value, the grid is the
 //     sample's own (2-D for the x and z passes).
@@ -175,11 +185,17 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
                         const float *ms_map, const float *h_map, uint32_t terms, int mode,
                         float dt, int renorm, float *out_m, float *out_h, int *flag, hipStream_t s);
 // a5-a8 in one launch: x-inverse of S1 (H_demag kept on chip) + local terms +
-// Euler step of m into out_m; for uniform Ms, nx % 4 == 0 and Px <= 512
+// Euler step of m into out_m; for uniform Ms, 8 <= Px <= 512 and nx <= Px/2
 // (fused_xinv_euler_ok)
 bool fused_xinv_euler_ok(const Geo &g);
 hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
                              const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s);
+// the same for many samples of one padded x length Px and one update width
+// (vec: nx % 4 == 0); every sample fused_xinv_euler_ok
+hipError_t launch_xinv_euler_table(const Table<XeDesc> &t, int Px, bool vec, const LocalParams &p, float dt,
+                                   int renorm, int *flag, hipStream_t s);
+// blocks of one sample's own grid of the fused pass
+long long xe_blocks(const Geo &g);
 // one Runge-Kutta stage (all field terms; coefficients in p.stage_*): reads
 // m (the stage state), Hd = H_demag(m), m_base and acc; writes out_m and acc
 hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, const float *Hd, const float *ms_map,

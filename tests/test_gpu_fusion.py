@@ -6,10 +6,12 @@ one pass by default (H_demag stays on chip); with the fusion switched off
 they run as the x-inverse kernel (H_demag to device memory) and the update
 kernel.  Both evaluate the same transform and the same update arithmetic, so
 every state after n steps must agree bit for bit: ragged y tiles, z-planes
-whose tile count is odd, every x transform length up to 256, anisotropy, a
-uniform and a mapped external field, the time-dependent field and graph
-replays.  Samples the fused pass does not cover (nx not a multiple of 4)
-take the two kernels either way.
+whose tile count is odd, every x transform length up to 256, nx a multiple
+of 4 (4 cells per thread) or not (odd and even nx, one cell at a time),
+anisotropy, a uniform and a mapped external field, the time-dependent field,
+graph replays, and batches (every group of samples with one padded x length
+and update width as one launch).  Samples the fused pass does not cover
+(padded x length below 8) take the two kernels either way.
 
 Paper: Zhu, arXiv:1411.2565, Sec. 3 (demag field, local terms, Euler step
 of eq. (3)).
@@ -55,9 +57,11 @@ def run(gpu_lib, n, steps, fused, hmap=None, sched=None, flags=0, seed=5):
 
 
 # (nx, ny, nz): x transform lengths 4..256, ragged y tiles (ny % 8 != 0),
-# odd tile counts and z-plane counts that break the paired block order
+# odd tile counts and z-plane counts that break the paired block order; nx
+# not a multiple of 4, odd or even
 SIZES = [(4, 3, 2), (8, 8, 1), (16, 16, 2), (20, 12, 3), (32, 32, 4), (64, 24, 5), (100, 9, 2),
-         (128, 128, 4), (256, 40, 3), (256, 256, 32)]
+         (128, 128, 4), (256, 40, 3), (256, 256, 32), (3, 4, 2), (7, 5, 3), (18, 10, 2), (13, 9, 2),
+         (66, 17, 3), (255, 20, 2), (6, 12, 140)]
 
 
 @pytest.mark.parametrize("n", SIZES, ids=lambda n: "x".join(map(str, n)))
@@ -75,7 +79,7 @@ def test_fused_step_equals_two_kernel_step(gpu_lib, n):
 
 def test_unfusable_sample_takes_two_kernels(gpu_lib):
     import torch
-    n = (18, 10, 2)  # nx % 4 != 0
+    n = (2, 6, 3)  # padded x length 4
     a, _, ta = run(gpu_lib, n, 5, True)
     b, _, _ = run(gpu_lib, n, 5, False)
     assert torch.equal(a, b)
@@ -117,3 +121,30 @@ def test_fused_graph_replays_equal_eager_two_kernel_steps(gpu_lib):
             assert torch.equal(graph, eager), rep
         fused.close()
         split.close()
+
+
+def test_batch_fused_equals_two_kernel_steps(gpu_lib):
+    """The 64 films (groups by padded x length 256 / 512 and nx % 4): 20
+    steps with the fused launches, eager and replaying 32-step graphs on a
+    stream of its own, against 20 eager two-kernel steps, bit for bit."""
+    import torch
+    films = workloads.batch_films(count=64, seed=0)
+    w0 = films[0][0]
+    hs = [tuple(h) for (_, _, h) in films]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        B = gpu_lib.Batch([w.n for (w, _, _) in films], w0.d, Ms=w0.Ms, A=w0.A, alpha=w0.alpha, hext=hs)
+        a = B.pack([m0 for (_, m0, _) in films])
+        b, c = a.clone(), a.clone()
+        B.set_fusion(True)
+        B.step(a, 20, w0.dt)
+        B.step(c, 64, w0.dt, gpu_lib.MM_F_GRAPH)
+        B.set_fusion(False)
+        B.step(b, 20, w0.dt)
+        d = b.clone()
+        B.step(d, 44, w0.dt)
+        B.sync()
+        assert torch.isfinite(a).all()
+        assert torch.equal(a, b)
+        assert torch.equal(c, d)
+        B.close()
