@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel sources whose SHA-256 is
 # recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 680.3 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258097792,
-              "source_sha": "7437f31deea9c5392e33f72ffcdd8f6be6f3d4ea2b178a6e21e3463532b9a3b7"},
+    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 681.1 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258099456,
+              "source_sha": "459d1034f40f594edbd958f5ff3e733b35884344fc7da9b5c6d59687d24a3be2"},
 }
 
 def kernel_source_sha():
@@ -85,7 +85,9 @@ def kernel_bytes(n, P):
     complex64 spectra, each array read or written once; the tensor spectrum
     is the real octant, 6 floats per stored frequency).  Unfused, the
     x-inverse writes H_demag and the local kernel reads it back; the fused
-    x-inverse + update reads S1 and m and writes m."""
+    x-inverse + update reads S1 and m and writes m; chained with the next
+    step's x-forward it also writes S1 (and that step's x-forward, which
+    reads m, does not run)."""
     nx, ny, nz = n
     Px, Py, Pz = P
     Hx = Px // 2 + 1
@@ -97,7 +99,7 @@ def kernel_bytes(n, P):
     s2 = 8 * 3 * nz * Hx * Py
     k = 4 * 6 * Hx * Hy * Hz
     return {"xfwd": m + s1, "yfwd": s1 + s2, "zconv": 2 * s2 + k, "yinv": s2 + s1,
-            "xinv": s1 + m, "local": 3 * m, "xinv_local": s1 + 2 * m}
+            "xinv": s1 + m, "local": 3 * m, "xinv_local": s1 + 2 * m, "xinv_local_xfwd": 2 * s1 + 2 * m}
 
 
 def model_bytes(n, P):
@@ -112,7 +114,7 @@ def unfused_leg(binding, sim, m, w, flags, args):
     """The same steps with the x-inverse and the update as two kernels
     (H_demag written and read back): settle, time, then per-kernel events."""
     import torch
-    binding.mm_set_fusion(sim.ctx, False)
+    binding.mm_set_fusion(sim.ctx, 0)
     sim.step(m, args.settle_steps + args.warmup, w.dt, flags)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -123,7 +125,7 @@ def unfused_leg(binding, sim, m, w, flags, args):
     sim.step(m, args.profile_steps, w.dt, flags)
     times = binding.mm_kernel_times(sim.ctx)
     binding.mm_kernel_timing(sim.ctx, False)
-    binding.mm_set_fusion(sim.ctx, True)
+    binding.mm_set_fusion(sim.ctx, 0 if args.no_fusion else args.fusion_level)
     sim.sync()
     return {"us_per_step": round(us, 2),
             "kernels_us": {k: round(1e3 * tot / cnt, 2) for k, (tot, cnt) in times.items() if cnt}}
@@ -520,6 +522,8 @@ def main():
                     help="run the headline timing with the compensated spectral multiply")
     ap.add_argument("--no-fusion", action="store_true",
                     help="run the headline timing with the x-inverse and the update as two kernels")
+    ap.add_argument("--fusion-level", type=int, default=1, choices=(1, 2),
+                    help="1: x-inverse + update fused; 2: also the next step's x-forward")
     ap.add_argument("--no-unfused-leg", action="store_true",
                     help="skip the timing of the two-kernel (unfused) step")
     ap.add_argument("--no-compensated-leg", action="store_true",
@@ -559,7 +563,7 @@ def main():
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t
     m = torch.tensor(m0, dtype=torch.float32, device=dev)
-    binding.mm_set_fusion(sim.ctx, not args.no_fusion)
+    binding.mm_set_fusion(sim.ctx, 0 if args.no_fusion else args.fusion_level)
 
     print(f"bench: {args.settle_steps} settle + {args.warmup} warm-up steps", file=sys.stderr, flush=True)
     sim.step(m, args.settle_steps, w.dt, flags)
@@ -595,7 +599,9 @@ def main():
                       "GBps": round(kb[k] / (avg_us * 1e-6) / 1e9, 1) if cnt else None}
     dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
     ach = kernels[dom]["GBps"]
-    step_bytes_impl = sum(kb[k] for k, v in kernels.items() if v["launches"])
+    # bytes per step of the kernels that ran (launch counts over the region:
+    # with the chained x-forward, the x-forward runs once per call)
+    step_bytes_impl = sum(kb[k] * v["launches"] for k, v in kernels.items()) / max(args.profile_steps, 1)
     step_bytes = model_bytes(w.n, P)
 
     unfused = None
@@ -666,7 +672,7 @@ def main():
         "config": {"workload": "block 256x256x32 cells, 5 nm cubes, padded FFT 512x512x64",
                    "cells": w.N, "dt": w.dt, "alpha": w.alpha, "Ms": w.Ms, "A": w.A,
                    "spectral_multiply": "compensated" if args.compensated else "plain",
-                   "fused_xinv_update": not args.no_fusion},
+                   "fusion_level": 0 if args.no_fusion else args.fusion_level},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)},
         "cpu_baseline": cpu,

@@ -254,8 +254,9 @@ def mm_sync(ctx):
     _check(ctx, load().mm_sync(ctx), "mm_sync")
 
 
-def mm_set_fusion(ctx, on):
-    _check(ctx, load().mm_set_fusion(ctx, int(bool(on))), "mm_set_fusion")
+def mm_set_fusion(ctx, level):
+    """0: two kernels; 1: x-inverse + update fused; 2: also the next x-forward."""
+    _check(ctx, load().mm_set_fusion(ctx, int(level)), "mm_set_fusion")
 
 
 def mm_set_compensated(ctx, on):
@@ -314,7 +315,7 @@ def mm_adjoint_step(ctx, m_n, hd_n, lam, g_hext, g_ms, dt, flags, N):
            "mm_adjoint_step")
 
 
-MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local", "xinv_local"]
+MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local", "xinv_local", "xinv_local_xfwd"]
 
 
 def mm_kernel_timing(ctx, enable):

@@ -54,7 +54,7 @@ struct mm_ctx {
     size_t o_K = 0, o_S1 = 0, o_S2 = 0, o_mtmp = 0, o_rk = 0, o_T = 0, o_tA = 0, o_tB = 0;
     size_t o_ms = 0, o_h = 0, o_part = 0, o_lpart = 0, o_flag = 0, o_adj = 0, total = 0;
     bool compensated = false;  // compensated spectral multiply in every demag evaluation
-    bool fusion = true;        // Euler steps run the x-inverse and the update as one kernel where it applies
+    int fusion = 1;            // Euler steps: 0 two kernels, 1 x-inverse + update fused, 2 also the next x-forward
     bool vacuum = false;       // the Ms map holds vacuum cells (Ms = 0)
     int tune[3] = {0, 0, 0};   // launch-shape variants of the x, y and z passes
     // time-dependent external field: profile times, and which slot of the
@@ -290,7 +290,7 @@ const float *h_map_ptr(const mm_ctx *c) { return c->h_map ? c->at<float>(c->o_h)
 // The demag spectrum of m (M = Ms m, or M = m when unit_ms): the x-forward,
 // y-forward, z-convolution and y-inverse passes, leaving H_demag's x spectrum
 // in S1.
-mm_status demag_spectrum(mm_ctx *c, const float *m, bool comp, bool unit_ms = false)
+mm_status demag_spectrum(mm_ctx *c, const float *m, bool comp, bool unit_ms = false, bool have_s1 = false)
 {
     const mmk::Geo &g = c->g;
     float2 *S1 = c->at<float2>(c->o_S1), *S2 = c->at<float2>(c->o_S2);
@@ -300,7 +300,8 @@ mm_status demag_spectrum(mm_ctx *c, const float *m, bool comp, bool unit_ms = fa
     const float ms = unit_ms ? 1.0f : (float)c->mat.Ms;
     comp = comp || c->compensated;
     const int *tv = c->tune;
-    MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, msm, ms, S1, s, tv[0]); }));
+    if (!have_s1)  // else S1 already holds m's x spectrum (the previous step's chained x-forward)
+        MM_TRY(timed(c, MM_K_XFWD, "xfwd", [&] { return mmk::launch_xfwd(g, m, msm, ms, S1, s, tv[0]); }));
     MM_TRY(timed(c, MM_K_YFWD, "yfwd", [&] { return mmk::launch_yfwd(g, S1, S2, s, tv[1]); }));
     MM_TRY(timed(c, MM_K_ZCONV, "zconv", [&] { return mmk::launch_zconv(g, S2, K, comp, s, tv[2]); }));
     MM_TRY(timed(c, MM_K_YINV, "yinv", [&] { return mmk::launch_yinv(g, S2, S1, s, tv[1]); }));
@@ -620,20 +621,28 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
     }
     p.dt64 = dt;
     // the x-inverse and the update as one pass (H_demag stays on chip), unless
-    // H_demag is to be stored or an Ms map is set
-    const bool fuse = c->fusion && !c->ms_map && mmk::fused_xinv_euler_ok(c->g);
+    // H_demag is to be stored or an Ms map is set; at fusion level 2 that
+    // pass also runs the next step's x-forward of the state it writes (when
+    // the next step is fused too), so that step skips its own x-forward
+    const bool fuse = c->fusion >= 1 && !c->ms_map && mmk::fused_xinv_euler_ok(c->g);
+    const bool chain = fuse && c->fusion >= 2;
+    bool have_s1 = false;
     for (int64_t s = 0; s < nsteps; ++s) {
         float *hs = hd(s);
         if (fuse && !hs) {
-            MM_TRY(demag_spectrum(c, src(s), comp));
+            MM_TRY(demag_spectrum(c, src(s), comp, false, have_s1));
             p.tslot = c->tslot;
             if (c->sched) c->tslot ^= 1;  // this step's kernel writes the next step's time
-            MM_TRY(timed(c, MM_K_XINV_LOCAL, "x-inverse + llg step", [&] {
-                return mmk::launch_xinv_euler(c->g, p, c->at<float2>(c->o_S1), src(s), h_map_ptr(c), (float)dt,
-                                              renorm, dst(s), flag, c->stream);
+            const bool xf = chain && s + 1 < nsteps && !hd(s + 1);
+            float2 *S1 = c->at<float2>(c->o_S1);
+            MM_TRY(timed(c, xf ? MM_K_XINV_LOCAL_XFWD : MM_K_XINV_LOCAL, "x-inverse + llg step", [&] {
+                return mmk::launch_xinv_euler(c->g, p, S1, src(s), h_map_ptr(c), (float)dt, renorm, dst(s), flag,
+                                              c->stream, xf ? S1 : nullptr);
             }));
+            have_s1 = xf;
             continue;
         }
+        have_s1 = false;
         float *Hd = nullptr;
         MM_TRY(demag(c, src(s), comp, &Hd, hs));
         p.tslot = c->tslot;
@@ -977,7 +986,8 @@ mm_status mm_autotune(mm_ctx *c, const char *cache_path, int32_t choice_out[3])
 mm_status mm_set_fusion(mm_ctx *c, int on)
 {
     if (!c) return MM_EINVAL;
-    c->fusion = on != 0;
+    if (on < 0 || on > 2) return fail(c, MM_EINVAL, "fusion level %d outside [0, 2]", on);
+    c->fusion = on;
     c->drop_graphs();
     return MM_OK;
 }
@@ -1408,7 +1418,7 @@ std::vector<char> plan_image(const mm_batch *b, const float *m)
                         put(L.o_desc[0] + sizeof(zd) * k, &zd, sizeof(zd));
                     }
                 } else if (L.pass == 4) {
-                    const mmk::XeDesc xe{sm.g, b->at<float2>(sm.o_S1), src, nullptr, dst,
+                    const mmk::XeDesc xe{sm.g, b->at<float2>(sm.o_S1), src, nullptr, dst, nullptr,
                                          (float)sm.h[0], (float)sm.h[1], (float)sm.h[2], 0};
                     put(L.o_desc[par] + sizeof(xe) * k, &xe, sizeof(xe));
                 } else {

@@ -967,16 +967,15 @@ __device__ __forceinline__ void local_field(const LocalDesc &D, const LocalParam
     }
 }
 
-// Explicit Euler step of V cells with the field h (mode 1 of k_local): writes
-// P(m + dt f) to out_m, P the renormalisation unless renorm = 0; vacuum cells
-// keep their state.  Sets *flag on a non-finite result.
+// Explicit Euler step of V cells with the field h (mode 1 of k_local): o =
+// P(m + dt f), P the renormalisation unless renorm = 0; vacuum cells keep
+// their state; bad is set on a non-finite result.  euler_store writes o to
+// out_m and sets *flag.
 template <int V>
-__device__ __forceinline__ void euler_store(const LocalParams &p, float dt, int renorm, const float (&mc)[3][V],
-                                            const float (&h)[3][V], const bool (&mag)[V], float *__restrict__ out_m,
-                                            long long N, long long i0, int *__restrict__ flag)
+__device__ __forceinline__ void euler_next(const LocalParams &p, float dt, int renorm, const float (&mc)[3][V],
+                                           const float (&h)[3][V], const bool (&mag)[V], float (&o)[3][V],
+                                           bool &bad)
 {
-    float o[3][V];
-    bool bad = false;
 #pragma unroll
     for (int j = 0; j < V; ++j) {
         const float mx = mc[0][j], my = mc[1][j], mz = mc[2][j];
@@ -1004,6 +1003,16 @@ __device__ __forceinline__ void euler_store(const LocalParams &p, float dt, int 
         o[1][j] = ny_;
         o[2][j] = nz_;
     }
+}
+
+template <int V>
+__device__ __forceinline__ void euler_store(const LocalParams &p, float dt, int renorm, const float (&mc)[3][V],
+                                            const float (&h)[3][V], const bool (&mag)[V], float *__restrict__ out_m,
+                                            long long N, long long i0, int *__restrict__ flag)
+{
+    float o[3][V];
+    bool bad = false;
+    euler_next<V>(p, dt, renorm, mc, h, mag, o, bad);
     if (bad) *flag = 1;
 #pragma unroll
     for (int c = 0; c < 3; ++c) vstore<V>(out_m + c * N + i0, o[c]);
@@ -1194,13 +1203,14 @@ struct XEShape {
     static constexpr int THREADS = NL * T;
     static constexpr int LD = lds_line(L);
     static constexpr int LDS = NL * LD + L + 1;  // line buffers + unpack twiddles (complex)
-    // H_demag of the block's cells ([3][LPB][nx] floats, nx <= L) fits in the line buffers
-    static_assert(3 * LPB * L <= 2 * NL * LD, "H_demag tile exceeds the line buffers");
+    // H_demag and the next state of the block's cells ([3][LPB][nx] floats
+    // each, nx <= L) fit in the line buffers
+    static_assert(6 * LPB * L <= 2 * NL * LD, "H_demag and state tiles exceed the line buffers");
     // one thread per 4 cells of the LPB rows of nx <= L cells
     static_assert(LPB * L / 4 <= THREADS, "too few threads for the update");
 };
 
-template <int L, int LPB_, int V, bool TAB>
+template <int L, int LPB_, int V, bool TAB, bool XF>
 __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(PassArg<XeDesc, TAB> A, LocalParams p,
                                                                            float dt, int renorm,
                                                                            int *__restrict__ flag)
@@ -1308,21 +1318,37 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
         }
     }
     __syncthreads();
+    // XF: the next state of the tile's cells also goes to LDS ([3][LPB][nx]
+    // floats after H_demag), for the next step's x-forward below
+    float *const sM = sH + 3 * LPB * g.nx;
     if constexpr (V == 4) {
-        if (!upd) return;  // no barrier follows
-        float h[3][4];
+        if (upd) {
+            float h[3][4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float4 hv = *reinterpret_cast<const float4 *>(sH + (c * LPB + yl_u) * g.nx + x0);
-            h[c][0] = hv.x;
-            h[c][1] = hv.y;
-            h[c][2] = hv.z;
-            h[c][3] = hv.w;
+            for (int c = 0; c < 3; ++c) {
+                const float4 hv = *reinterpret_cast<const float4 *>(sH + (c * LPB + yl_u) * g.nx + x0);
+                h[c][0] = hv.x;
+                h[c][1] = hv.y;
+                h[c][2] = hv.z;
+                h[c][3] = hv.w;
+            }
+            bool mag[4];
+            float inv_ms[4];
+            local_field<4, false, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
+            if constexpr (XF) {
+                float o[3][4];
+                bool bad = false;
+                euler_next<4>(p, dt, renorm, mc, h, mag, o, bad);
+                if (bad) *flag = 1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    vstore<4>(D.m_out + c * g.N + i0, o[c]);
+                    vstore<4>(sM + (c * LPB + yl_u) * g.nx + x0, o[c]);
+                }
+            } else {
+                euler_store<4>(p, dt, renorm, mc, h, mag, D.m_out, g.N, i0, flag);
+            }
         }
-        bool mag[4];
-        float inv_ms[4];
-        local_field<4, false, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
-        euler_store<4>(p, dt, renorm, mc, h, mag, D.m_out, g.N, i0, flag);
     } else {
         for (int wi = threadIdx.x; wi < nl * g.nx; wi += S::THREADS) {
             const int yl = wi / g.nx, x = wi - yl * g.nx;
@@ -1333,7 +1359,68 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
             bool mag[1];
             float inv_ms[1];
             local_field<1, false>(DL, p, 15u, hsc, i, x, y0 + yl, z, m1, h1, mag, inv_ms);
-            euler_store<1>(p, dt, renorm, m1, h1, mag, D.m_out, g.N, i, flag);
+            if constexpr (XF) {
+                float o[3][1];
+                bool bad = false;
+                euler_next<1>(p, dt, renorm, m1, h1, mag, o, bad);
+                if (bad) *flag = 1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    D.m_out[c * g.N + i] = o[c][0];
+                    sM[(c * LPB + yl) * g.nx + x] = o[c][0];
+                }
+            } else {
+                euler_store<1>(p, dt, renorm, m1, h1, mag, D.m_out, g.N, i, flag);
+            }
+        }
+    }
+    if constexpr (XF) {
+        // the next step's x-forward of the tile (the arithmetic of k_xfwd):
+        // line ll = (c, yl) packs Ms m into z[k] = r[2k] + i r[2k+1], is
+        // transformed, unpacked to the half spectrum and stored in place of
+        // this step's S1 tile, which only this block reads
+        __syncthreads();
+        // this phase's thread index comes from an empty asm statement: the
+        // compiler then recomputes its addresses and twiddles here instead of
+        // keeping those of the tile load and the first transform live
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int l2 = tid / T, t2 = tid - l2 * T;
+        TwSet<L, E> tw2;
+        load_twiddles<L, E>(tw2, t2);
+        float2 u[1][E];
+        {
+            const int c = l2 / LPB, yl = l2 - c * LPB;
+            const float *row = sM + (c * LPB + yl) * g.nx;
+#pragma unroll
+            for (int q = 0; q < E; ++q) {
+                const int xx = 2 * (t2 + q * T);
+                float2 a = make_float2(0.f, 0.f);
+                if (q < half_elems(E) && yl < nl && xx < g.nx) {
+                    a.x = row[xx];
+                    if (xx + 1 < g.nx) a.y = row[xx + 1];
+                }
+                u[0][q] = q < half_elems(E) ? make_float2(a.x * p.ms, a.y * p.ms) : make_float2(0.f, 0.f);
+            }
+        }
+        __syncthreads();  // every row is read before the transforms reuse the buffers
+        float2 *const lds2[1] = {sm + l2 * LD};
+        reg_fft<L, false, MMK_WAVE_FFT && (T <= 64)>(u, lds2, t2, tw2);
+#pragma unroll
+        for (int q = 0; q < E; ++q) sm[l2 * LD + t2 + q * T] = u[0][q];
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int idx = tid + it * S::THREADS;
+            const int kx = idx / NL, r = idx - kx * NL;
+            const int c = r / LPB, yl = r - c * LPB;
+            if (idx >= (L + 1) * NL || yl >= nl) continue;
+            const float2 *Z = sm + r * LD;
+            const float2 zk = Z[kx & (L - 1)];
+            const float2 zc = cconj(Z[(L - kx) & (L - 1)]);
+            const float2 Ev = cscale(cadd(zk, zc), 0.5f);
+            const float2 Od = mul_mi<false>(cscale(csub(zk, zc), 0.5f));
+            D.S1w[(((long long)c * g.nz + z) * g.Hx + kx) * g.ny + y0 + yl] = cadd(Ev, cmul(tw[kx], Od));
         }
     }
 }
@@ -2221,7 +2308,7 @@ long long xe_blocks(const Geo &g)
     return (long long)g.nz * ((g.ny + MMK_XE_LPB - 1) / MMK_XE_LPB);
 }
 
-template <bool TAB>
+template <bool TAB, bool XF>
 static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px, bool vec, const LocalParams &p,
                                 float dt, int renorm, int *flag, hipStream_t s)
 {
@@ -2232,11 +2319,11 @@ static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px
             using S = XEShape<LL, MMK_XE_LPB>;                                                \
             const size_t lds = S::LDS * sizeof(float2);                                       \
             if (vec)                                                                          \
-                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 4, TAB>), grid, dim3(S::THREADS), lds, s, a, p, dt, \
-                           renorm, flag);                                                     \
+                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 4, TAB, XF>), grid, dim3(S::THREADS), lds, s, a, p, \
+                           dt, renorm, flag);                                                 \
             else                                                                              \
-                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 1, TAB>), grid, dim3(S::THREADS), lds, s, a, p, dt, \
-                           renorm, flag);                                                     \
+                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 1, TAB, XF>), grid, dim3(S::THREADS), lds, s, a, p, \
+                           dt, renorm, flag);                                                 \
             return hipGetLastError();                                                         \
         }                                                                                     \
         break;                                                                                \
@@ -2250,18 +2337,21 @@ static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px
 }
 
 hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
-                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s)
+                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s,
+                             float2 *S1_next)
 {
-    if (!fused_xinv_euler_ok(g)) return hipErrorInvalidValue;
-    const PassArg<XeDesc, false> a{XeDesc{g, S1, m, h_map, out_m, p.h0, p.h1, p.h2, 0}};
-    return launch_xe_any(a, dim3((unsigned)xe_blocks(g)), g.Px, g.nx % 4 == 0, p, dt, renorm, flag, s);
+    if (!fused_xinv_euler_ok(g) || (S1_next && S1_next != S1)) return hipErrorInvalidValue;
+    const PassArg<XeDesc, false> a{XeDesc{g, S1, m, h_map, out_m, S1_next, p.h0, p.h1, p.h2, 0}};
+    const dim3 grid((unsigned)xe_blocks(g));
+    if (S1_next) return launch_xe_any<false, true>(a, grid, g.Px, g.nx % 4 == 0, p, dt, renorm, flag, s);
+    return launch_xe_any<false, false>(a, grid, g.Px, g.nx % 4 == 0, p, dt, renorm, flag, s);
 }
 
 hipError_t launch_xinv_euler_table(const Table<XeDesc> &t, int Px, bool vec, const LocalParams &p, float dt,
                                    int renorm, int *flag, hipStream_t s)
 {
     if (!table_ok(t)) return hipErrorInvalidValue;
-    return launch_xe_any(targ(t), tgrid(t), Px, vec, p, dt, renorm, flag, s);
+    return launch_xe_any<true, false>(targ(t), tgrid(t), Px, vec, p, dt, renorm, flag, s);
 }
 
 struct OpMax {

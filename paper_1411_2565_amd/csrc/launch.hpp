@@ -78,12 +78,14 @@ struct LocalDesc {
     int perm_q;           // set by the launcher: blocks per XCD per z-plane of the block order (0: launch order)
 };
 // The fused x-inverse + Euler update of one sample: H_demag's x spectrum S1
-// in, the state m read, the next state m_out written.
+// in, the state m read, the next state m_out written; with the chained
+// x-forward, the next step's S1 (of m_out) written to S1w (the same array).
 struct XeDesc {
     Geo g;
     const float2 *S1;
     const float *m, *h_map;
     float *m_out;
+    float2 *S1w;
     float h0, h1, h2;  // uniform external field of this sample (no map)
     int pad;
 };
@@ -188,8 +190,11 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
 // Euler step of m into out_m; for uniform Ms, 8 <= Px <= 512 and nx <= Px/2
 // (fused_xinv_euler_ok)
 bool fused_xinv_euler_ok(const Geo &g);
+// S1_next != NULL: the launch also runs the next step's x-forward of out_m
+// (as launch_xfwd with Ms = p.ms) into S1_next, which must be S1 itself
 hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
-                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s);
+                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s,
+                             float2 *S1_next = nullptr);
 // the same for many samples of one padded x length Px and one update width
 // (vec: nx % 4 == 0); every sample fused_xinv_euler_ok
 hipError_t launch_xinv_euler_table(const Table<XeDesc> &t, int Px, bool vec, const LocalParams &p, float dt,

@@ -44,6 +44,12 @@ def test_byte_model_of_the_block_step():
     # the fused tail does not write H_demag and read it back: 2 x 25.17 MB
     h_round_trip = 2 * 4 * 3 * 256 * 256 * 32
     assert abs(kb["xinv"] + kb["local"] - h_round_trip - kb["xinv_local"]) == 0
+    # chaining the next step's x-forward into the fused pass saves that
+    # x-forward's read of m (25.17 MB): 709.0 MB per step in steady state
+    m_bytes = 4 * 3 * 256 * 256 * 32
+    assert kb["xfwd"] + kb["xinv_local"] - kb["xinv_local_xfwd"] == m_bytes
+    chained = kb["yfwd"] + kb["zconv"] + kb["yinv"] + kb["xinv_local_xfwd"]
+    assert abs(chained / 1e6 - 708.98) < 0.01
     # the headline fraction of HBM peak is taken on that 734.15 MB model
     assert abs(bench.model_bytes((256, 256, 32), (512, 512, 64)) / 1e6 - 734.15) < 0.1
 

@@ -2,9 +2,11 @@
 C ABI.
 
 Euler steps run the x-inverse transform, the local terms and the update as
-one pass by default (H_demag stays on chip); with the fusion switched off
-they run as the x-inverse kernel (H_demag to device memory) and the update
-kernel.  Both evaluate the same transform and the same update arithmetic, so
+one pass (fusion level 1: H_demag stays on chip), and by default (level 2)
+that pass also runs the next step's x-forward transform of the state it
+writes, so the next step skips its own; at level 0 they run as the
+x-inverse kernel (H_demag to device memory) and the update kernel.  All
+levels evaluate the same transforms and the same update arithmetic, so
 every state after n steps must agree bit for bit: ragged y tiles, z-planes
 whose tile count is odd, every x transform length up to 256, nx a multiple
 of 4 (4 cells per thread) or not (odd and even nx, one cell at a time),
@@ -29,11 +31,11 @@ def gpu(x):
     return torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda:0")
 
 
-def run(gpu_lib, n, steps, fused, hmap=None, sched=None, flags=0, seed=5):
+def run(gpu_lib, n, steps, level, hmap=None, sched=None, flags=0, seed=5, timed_steps=1):
     rng = np.random.default_rng(seed)
     sim = gpu_lib.Sim(n, (4e-9, 5e-9, 3e-9), Ms=8.0e5, A=1.3e-11, Ku=5e4, u=(0.6, 0.0, 0.8), alpha=0.3,
                       hext=(2e4, -1e4, 3e4))
-    gpu_lib.mm_set_fusion(sim.ctx, fused)
+    gpu_lib.mm_set_fusion(sim.ctx, level)
     hm = None  # the context keeps the map's pointer: hold the tensor until the end
     if hmap is not None:
         hm = gpu(hmap)
@@ -47,7 +49,7 @@ def run(gpu_lib, n, steps, fused, hmap=None, sched=None, flags=0, seed=5):
     t = sim.time() if sched is not None else None
     times = None
     gpu_lib.mm_kernel_timing(sim.ctx, True)
-    sim.step(m, 1, 2e-14, flags)
+    sim.step(m, timed_steps, 2e-14, flags)
     times = gpu_lib.mm_kernel_times(sim.ctx)
     gpu_lib.mm_kernel_timing(sim.ctx, False)
     sim.sync()
@@ -68,20 +70,35 @@ SIZES = [(4, 3, 2), (8, 8, 1), (16, 16, 2), (20, 12, 3), (32, 32, 4), (64, 24, 5
 def test_fused_step_equals_two_kernel_step(gpu_lib, n):
     import torch
     steps = 3 if n == (256, 256, 32) else 7
-    a, _, ta = run(gpu_lib, n, steps, True)
-    b, _, tb = run(gpu_lib, n, steps, False)
+    c, _, tc = run(gpu_lib, n, steps, 2, timed_steps=3)
+    a, _, ta = run(gpu_lib, n, steps, 1, timed_steps=3)
+    b, _, tb = run(gpu_lib, n, steps, 0, timed_steps=3)
     assert torch.isfinite(a).all()
-    assert torch.equal(a, b), f"{n}: max |diff| {(a - b).abs().max().item():.3e}"
-    # the fused pass really ran (one launch per step) and the unfused did not
-    assert ta["xinv_local"][1] == 1 and ta["xinv"][1] == 0 and ta["local"][1] == 0
-    assert tb["xinv_local"][1] == 0 and tb["xinv"][1] == 1 and tb["local"][1] == 1
+    assert torch.equal(a, b), f"{n}: level 1 vs 0 max |diff| {(a - b).abs().max().item():.3e}"
+    assert torch.equal(c, b), f"{n}: level 2 vs 0 max |diff| {(c - b).abs().max().item():.3e}"
+    # which passes ran over a 3-step call: level 2 chains the x-forward of
+    # steps 2 and 3 into the fused passes of steps 1 and 2
+    assert tc["xfwd"][1] == 1 and tc["xinv_local_xfwd"][1] == 2 and tc["xinv_local"][1] == 1
+    assert tc["xinv"][1] == 0 and tc["local"][1] == 0
+    assert ta["xfwd"][1] == 3 and ta["xinv_local"][1] == 3 and ta["xinv_local_xfwd"][1] == 0
+    assert ta["xinv"][1] == 0 and ta["local"][1] == 0
+    assert tb["xinv_local"][1] == 0 and tb["xinv_local_xfwd"][1] == 0 and tb["xinv"][1] == 3
+    assert tb["local"][1] == 3
+
+
+def test_fusion_level_is_checked(gpu_lib):
+    sim = gpu_lib.Sim((8, 8, 2), (5e-9,) * 3, Ms=8e5, A=1.3e-11)
+    for bad in (-1, 3):
+        with pytest.raises(gpu_lib.MMError):
+            gpu_lib.mm_set_fusion(sim.ctx, bad)
+    sim.close()
 
 
 def test_unfusable_sample_takes_two_kernels(gpu_lib):
     import torch
     n = (2, 6, 3)  # padded x length 4
-    a, _, ta = run(gpu_lib, n, 5, True)
-    b, _, _ = run(gpu_lib, n, 5, False)
+    a, _, ta = run(gpu_lib, n, 5, 2)
+    b, _, _ = run(gpu_lib, n, 5, 0)
     assert torch.equal(a, b)
     assert ta["xinv_local"][1] == 0 and ta["xinv"][1] == 1 and ta["local"][1] == 1
 
@@ -92,8 +109,8 @@ def test_fused_step_with_field_map_and_schedule(gpu_lib, n):
     rng = np.random.default_rng(8)
     hmap = 4e4 * rng.standard_normal((3, n[2], n[1], n[0]))
     sched = (3e-14, 9e-14, 1.5e-13)  # on after 2 steps, decays from step 5, off after step 8
-    a, ta, _ = run(gpu_lib, n, 10, True, hmap=hmap, sched=sched)
-    b, tb, _ = run(gpu_lib, n, 10, False, hmap=hmap, sched=sched)
+    a, ta, _ = run(gpu_lib, n, 10, 2, hmap=hmap, sched=sched)
+    b, tb, _ = run(gpu_lib, n, 10, 0, hmap=hmap, sched=sched)
     assert torch.equal(a, b)
     assert ta == tb and abs(ta - 10 * 2e-14) < 1e-25
 
@@ -109,9 +126,9 @@ def test_fused_graph_replays_equal_eager_two_kernel_steps(gpu_lib):
     s = torch.cuda.Stream()
     kw = dict(Ms=8.0e5, A=1.3e-11, Ku=5e4, alpha=0.3, hext=(2e4, 0.0, 1e4))
     with torch.cuda.stream(s):
-        fused = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # fused steps in one captured graph
+        fused = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # fused steps (level 2) in one captured graph
         split = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # eager two-kernel steps
-        gpu_lib.mm_set_fusion(split.ctx, False)
+        gpu_lib.mm_set_fusion(split.ctx, 0)
         graph, eager = gpu(m0), gpu(m0)
         for rep in range(3):
             fused.step(graph, 20, 2e-14, gpu_lib.MM_F_GRAPH)
