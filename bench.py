@@ -171,6 +171,9 @@ def cpu_baseline(w, m0, target_s=12.0):
     el = time.perf_counter() - t
     return {"value": ncell / el, "unit": "cell-steps/s", "cores": oracle.threads(), "kind": "oracle",
             "cpu": cpu_model(),
+            # a full step of the block at this rate (every cell a direct sum
+            # over all sources): an extrapolation, not run
+            "full_step_s_extrapolated_not_run": round(w.N * el / ncell, 1),
             "sample": (f"one FP64 Euler step (direct-sum Newell demag over all {w.N} source cells + "
                        f"exchange/anisotropy/Zeeman + LLG) at {ncell} randomly sampled cells of the "
                        f"{w.n[0]}x{w.n[1]}x{w.n[2]} block; {el:.1f} s; tensor table build "
@@ -353,6 +356,32 @@ def timed_steps(sim, m, steps, dt, flags):
     sim.step(m, steps, dt, flags)
     torch.cuda.synchronize()
     return time.perf_counter() - t0
+
+
+def small_configs(binding):
+    """The two latency-bound workloads at their configured step counts: the
+    16x16x2 parity block (100 steps of 1e-13 s, repeated 20 times) and the
+    256x64x1 thin film (20 000 steps of 5e-14 s, its field applied): eager
+    launches and 32-step hipGraph chunks."""
+    import torch
+    from paper_1411_2565_amd import workloads
+    rows = []
+    s = torch.cuda.Stream()  # graph capture needs a non-default stream
+    for w, steps in ((workloads.BLOCK_16x16x2, 2000), (workloads.FILM_256x64x1, 20000)):
+        m0, h = workloads.inputs(w)
+        with torch.cuda.stream(s):
+            sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=w.Ku, u=w.u, alpha=w.alpha, hext=tuple(h), device=0)
+            m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+            sim.step(m, 64, w.dt, binding.MM_F_GRAPH)
+            sim.step(m, 64, w.dt)
+            te = timed_steps(sim, m, steps, w.dt, 0)
+            tg = timed_steps(sim, m, steps, w.dt, binding.MM_F_GRAPH)
+            sim.sync()
+            sim.close()
+        rows.append({"workload": w.name, "cells": w.N, "steps": steps, "dt": w.dt,
+                     "us_per_step": round(1e6 * te / steps, 2), "us_per_step_graph": round(1e6 * tg / steps, 2),
+                     "cell_steps_per_s": w.N * steps / min(te, tg)})
+    return rows
 
 
 def sweep_row(binding, w):
@@ -620,6 +649,9 @@ def main():
         print("bench: adjoint/forward ratio on the 128x128x4 film", file=sys.stderr, flush=True)
         adj = adjoint_ratio(binding)
 
+    print("bench: latency-bound workloads (16x16x2 block, 256x64x1 film)", file=sys.stderr, flush=True)
+    small = small_configs(binding)
+
     bat = None
     if not args.no_batch:
         print("bench: batched films", file=sys.stderr, flush=True)
@@ -688,6 +720,7 @@ def main():
         "tensor_build_s": round(t_build, 3),
         "adjoint": adj,
         "batch": bat,
+        "small_workloads": small,
         "size_sweep": sweep,
         "sp4": sp4,
         "integrators": rk,

@@ -60,10 +60,10 @@ def run(gpu_lib, n, steps, level, hmap=None, sched=None, flags=0, seed=5, timed_
 
 # (nx, ny, nz): x transform lengths 4..256, ragged y tiles (ny % 8 != 0),
 # odd tile counts and z-plane counts that break the paired block order; nx
-# not a multiple of 4, odd or even
+# not a multiple of 4, odd or even; single-cell y and z axes
 SIZES = [(4, 3, 2), (8, 8, 1), (16, 16, 2), (20, 12, 3), (32, 32, 4), (64, 24, 5), (100, 9, 2),
          (128, 128, 4), (256, 40, 3), (256, 256, 32), (3, 4, 2), (7, 5, 3), (18, 10, 2), (13, 9, 2),
-         (66, 17, 3), (255, 20, 2), (6, 12, 140)]
+         (66, 17, 3), (255, 20, 2), (6, 12, 140), (16, 1, 4), (9, 1, 1), (40, 7, 1)]
 
 
 @pytest.mark.parametrize("n", SIZES, ids=lambda n: "x".join(map(str, n)))
@@ -115,7 +115,8 @@ def test_fused_step_with_field_map_and_schedule(gpu_lib, n):
     assert ta == tb and abs(ta - 10 * 2e-14) < 1e-25
 
 
-def test_fused_graph_replays_equal_eager_two_kernel_steps(gpu_lib):
+@pytest.mark.parametrize("level", [1, 2])
+def test_fused_graph_replays_equal_eager_two_kernel_steps(gpu_lib, level):
     """Graph replays (capture needs a stream of its own) of fused steps,
     three replays with eager work and a synchronisation between them, each
     equal to the eager two-kernel steps."""
@@ -126,8 +127,9 @@ def test_fused_graph_replays_equal_eager_two_kernel_steps(gpu_lib):
     s = torch.cuda.Stream()
     kw = dict(Ms=8.0e5, A=1.3e-11, Ku=5e4, alpha=0.3, hext=(2e4, 0.0, 1e4))
     with torch.cuda.stream(s):
-        fused = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # fused steps (level 2) in one captured graph
+        fused = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # fused steps in one captured graph
         split = gpu_lib.Sim(n, (5e-9,) * 3, **kw)    # eager two-kernel steps
+        gpu_lib.mm_set_fusion(fused.ctx, level)
         gpu_lib.mm_set_fusion(split.ctx, 0)
         graph, eager = gpu(m0), gpu(m0)
         for rep in range(3):
