@@ -324,6 +324,16 @@ mm_status mm_forward_store(mm_ctx *c, float *m_dev, int64_t nsteps, double dt, u
 mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float *lam, float *g_hext,
                           float *g_ms, double dt, uint32_t flags);
 
+/* The adjoint of a stored segment of n >= 1 Euler steps (the same transpose
+ * as mm_adjoint_step, eq. (3) with the field of eq. (2)): m_traj and hd_traj
+ * as written by mm_forward_store for those n steps ([s][3][nz][ny][nx]),
+ * steps n-1 down to 0.  lam holds dL/dm_n on entry and dL/dm_0 on return;
+ * g_hext and g_ms accumulate as in mm_adjoint_step.  The same kernels in the
+ * same order as n calls of mm_adjoint_step, so the same results bit for bit,
+ * enqueued by one call. */
+mm_status mm_adjoint_segment(mm_ctx *c, const float *m_traj, const float *hd_traj, int64_t n, float *lam,
+                             float *g_hext, float *g_ms, double dt, uint32_t flags);
+
 /* Kernel identifiers for mm_kernel_times. */
 enum {
     MM_K_XFWD = 0,   /* x-forward real FFT (transposed write) */

@@ -79,6 +79,7 @@ def load():
                              ctypes.POINTER(ctypes.c_int64)],
         "mm_forward_store": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32, _P, _P],
         "mm_adjoint_step": [_P, _P, _P, _P, _P, _P, ctypes.c_double, ctypes.c_uint32],
+        "mm_adjoint_segment": [_P, _P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_double, ctypes.c_uint32],
         "mm_kernel_times": [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
         "mm_set_field_schedule": [_P, ctypes.POINTER(ctypes.c_double)],
         "mm_set_time": [_P, ctypes.c_double],
@@ -313,6 +314,18 @@ def mm_adjoint_step(ctx, m_n, hd_n, lam, g_hext, g_ms, dt, flags, N):
                                        _dev(hd_n, torch.float32, 3 * N, "hd_n"),
                                        _dev(lam, torch.float32, 3 * N, "lam"), gh, gm, float(dt), int(flags)),
            "mm_adjoint_step")
+
+
+def mm_adjoint_segment(ctx, m_traj, hd_traj, n, lam, g_hext, g_ms, dt, flags, N):
+    """n adjoint steps (n-1 down to 0) of a stored segment in one call."""
+    import torch
+    n = int(n)
+    gh = None if g_hext is None else _dev(g_hext, torch.float32, 3 * N, "g_hext")
+    gm = None if g_ms is None else _dev(g_ms, torch.float32, N, "g_ms")
+    _check(ctx, load().mm_adjoint_segment(ctx, _dev(m_traj, torch.float32, 3 * N * n, "m_traj"),
+                                          _dev(hd_traj, torch.float32, 3 * N * n, "hd_traj"), n,
+                                          _dev(lam, torch.float32, 3 * N, "lam"), gh, gm, float(dt), int(flags)),
+           "mm_adjoint_segment")
 
 
 MM_K_NAMES = ["xfwd", "yfwd", "zconv", "yinv", "xinv", "local", "xinv_local", "xinv_local_xfwd"]

@@ -1052,6 +1052,18 @@ mm_status mm_adjoint_step(mm_ctx *c, const float *m_n, const float *hd_n, float 
     });
 }
 
+mm_status mm_adjoint_segment(mm_ctx *c, const float *m_traj, const float *hd_traj, int64_t n, float *lam,
+                             float *g_hext, float *g_ms, double dt, uint32_t flags)
+{
+    if (!c) return MM_EINVAL;
+    if (n < 1) return fail(c, MM_EINVAL, "a segment has n >= 1 steps");
+    if (!m_traj || !hd_traj) return fail(c, MM_EINVAL, "m_traj and hd_traj must be device pointers");
+    const size_t S = 3 * (size_t)c->g.N;
+    for (int64_t s = n - 1; s >= 0; --s)
+        MM_TRY(mm_adjoint_step(c, m_traj + (size_t)s * S, hd_traj + (size_t)s * S, lam, g_hext, g_ms, dt, flags));
+    return MM_OK;
+}
+
 mm_status mm_reduce(mm_ctx *c, const float *m, double *out)
 {
     if (!c) return MM_EINVAL;

@@ -9,9 +9,11 @@ for any loss L(m_T), using the library's hand-written adjoint step.
 Memory: the forward keeps one state every S = ceil(sqrt(T)) steps.  The
 backward walks the segments from last to first; for each it replays the S
 forward steps from the checkpoint while storing every state and its
-demagnetising field (mm_forward_store), then runs S adjoint steps backwards
-(mm_adjoint_step).  The replay uses the same kernels in the same order as
-the forward pass, so the recomputed states are bitwise those of the forward.
+demagnetising field (mm_forward_store), then runs the S adjoint steps
+backwards in one call (mm_adjoint_segment).  The replay computes the same
+arithmetic as the forward pass (whose Euler steps fuse the x-inverse and the
+update, bit for bit equal to the replay's two passes), so the recomputed
+states are bitwise those of the forward.
 """
 import math
 
@@ -59,8 +61,7 @@ class LLGRollout(torch.autograd.Function):
             m = ctx.ckpts[idx].clone()
             sim._s()
             B.mm_forward_store(sim.ctx, m, n, dt, flags, mtraj[:n], hdtraj[:n], N)
-            for s in range(n - 1, -1, -1):
-                B.mm_adjoint_step(sim.ctx, mtraj[s], hdtraj[s], lam, g_h, g_ms, dt, flags, N)
+            B.mm_adjoint_segment(sim.ctx, mtraj[:n], hdtraj[:n], n, lam, g_h, g_ms, dt, flags, N)
         ctx.ckpts = None
         return lam, g_h, g_ms, None, None, None, None, None
 

@@ -88,6 +88,44 @@ def test_checkpointing_is_exact(gpu_lib):
         np.testing.assert_array_equal(x, y)
 
 
+def test_adjoint_segment_equals_single_steps(gpu_lib):
+    """mm_adjoint_segment over a stored 9-step segment equals nine calls of
+    mm_adjoint_step (steps 8 down to 0) bit for bit: lam, dL/dh_ext, dL/dMs."""
+    import torch
+    w, m0, ms, h, t = film_analogue((24, 20, 3))
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=3e3, u=(0.0, 0.6, 0.8), alpha=w.alpha)
+    hm, msm = gpu(h), gpu(ms)
+    sim.set_hext_map(hm)
+    sim.set_ms_map(msm)
+    N, n = sim.N, 9
+    m = gpu(m0)
+    mtraj = torch.empty((n, 3 * N), dtype=torch.float32, device="cuda:0")
+    hdtraj = torch.empty_like(mtraj)
+    gpu_lib.mm_forward_store(sim.ctx, m, n, 2e-14, 0, mtraj, hdtraj, N)
+    lam0 = gpu(np.random.default_rng(3).standard_normal((3, N)))
+    out = []
+    for seg in (False, True):
+        lam = lam0.clone()
+        g_h = torch.zeros_like(hm)
+        g_ms = torch.zeros_like(msm)
+        if seg:
+            gpu_lib.mm_adjoint_segment(sim.ctx, mtraj, hdtraj, n, lam, g_h, g_ms, 2e-14, 0, N)
+        else:
+            for s in range(n - 1, -1, -1):
+                gpu_lib.mm_adjoint_step(sim.ctx, mtraj[s], hdtraj[s], lam, g_h, g_ms, 2e-14, 0, N)
+        sim.sync()
+        out.append((lam, g_h, g_ms))
+    for a, b in zip(*out):
+        assert torch.isfinite(a).all()
+        assert torch.equal(a, b)
+    # a segment of no steps is an argument error (checked on the host)
+    import ctypes
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = gpu_lib.load().mm_adjoint_segment(sim.ctx, P(mtraj), P(hdtraj), 0, P(lam0), None, None, 2e-14, 0)
+    assert st == gpu_lib.MM_EINVAL
+    sim.close()
+
+
 def test_gradients_vs_fp64_central_differences(gpu_lib):
     """Directional derivatives of the loss along one random (h_x, h_y, h_z,
     Ms) direction in each of 32 random cells, FP64 central differences of
