@@ -233,20 +233,21 @@ mm_status mm_reduce_loss(mm_ctx *c, const float *m_dev, const float *target_dev,
 mm_status mm_reduce_loss_noalloc(mm_ctx *c, const float *m_dev, const float *target_dev, double *out_dev,
                                  float *grad_dev);
 
-/* Fusion level of the Euler steps of mm_step_llg (mm_forward_store, which
- * stores H_demag, does not fuse).  on = 0: the x-inverse transform and the
- * local terms + update run as two passes (H_demag through device memory).
- * on = 1 (the default): as one pass, so H_demag never goes to device
- * memory.  on = 2: that pass also runs the next step's x-forward transform
- * of the state it writes, for every step of a call but the last, so the
- * next step skips its own x-forward (m is not read twice; on the 256x256x32
- * block it took as long as level 1: 44.9 us against 27.1 + 16.4 us for the
- * two passes it replaces).  The fused pass applies to
- * samples with a uniform Ms and a padded x length Px with 8 <= Px <= 512
- * (nx >= 3); other samples always take two passes.  All levels give the
- * same result bit for bit (the same transform and update arithmetic).
- * MM_EINVAL for a level outside [0, 2].  Sec. 3: the demag field, the local
- * terms and the Euler step of eq. (3) per step. */
+/* Fusion level of the Euler steps of mm_step_llg and mm_forward_store.
+ * on = 0: the x-inverse transform and the local terms + update run as two
+ * passes (H_demag through device memory).  on = 1 (the default): as one
+ * pass, so H_demag never goes to device memory (mm_forward_store has that
+ * pass also store it for its trajectory).  on = 2: with a uniform Ms, that
+ * pass also runs the next step's x-forward transform of the state it
+ * writes, for every step of a call but the last, so the next step skips its
+ * own x-forward (m is not read twice; on the 256x256x32 block it took as
+ * long as level 1: 44.9 us against 27.1 + 16.4 us for the two passes it
+ * replaces).  The fused pass applies to samples with a padded x length Px
+ * with 8 <= Px <= 512 (nx >= 3), with or without an Ms map; other samples
+ * always take two passes.  All levels give the same result bit for bit
+ * (the same transform and update arithmetic).  MM_EINVAL for a level
+ * outside [0, 2].  Sec. 3: the demag field, the local terms and the Euler
+ * step of eq. (3) per step. */
 mm_status mm_set_fusion(mm_ctx *c, int on);
 
 /* Use (on != 0) or stop using the compensated FP32 spectral multiply in every

@@ -620,24 +620,24 @@ mm_status run_steps(mm_ctx *c, int64_t nsteps, double dt, uint32_t flags, Src sr
         return MM_OK;
     }
     p.dt64 = dt;
-    // the x-inverse and the update as one pass (H_demag stays on chip), unless
-    // H_demag is to be stored or an Ms map is set; at fusion level 2 that
-    // pass also runs the next step's x-forward of the state it writes (when
-    // the next step is fused too), so that step skips its own x-forward
-    const bool fuse = c->fusion >= 1 && !c->ms_map && mmk::fused_xinv_euler_ok(c->g);
-    const bool chain = fuse && c->fusion >= 2;
+    // the x-inverse and the update as one pass (H_demag stays on chip, and
+    // goes to hd(s) too where that is asked for); at fusion level 2 and a
+    // uniform Ms that pass also runs the next step's x-forward of the state
+    // it writes, so the next step skips its own x-forward
+    const bool fuse = c->fusion >= 1 && mmk::fused_xinv_euler_ok(c->g);
+    const bool chain = fuse && c->fusion >= 2 && !c->ms_map;
     bool have_s1 = false;
     for (int64_t s = 0; s < nsteps; ++s) {
         float *hs = hd(s);
-        if (fuse && !hs) {
+        if (fuse) {
             MM_TRY(demag_spectrum(c, src(s), comp, false, have_s1));
             p.tslot = c->tslot;
             if (c->sched) c->tslot ^= 1;  // this step's kernel writes the next step's time
-            const bool xf = chain && s + 1 < nsteps && !hd(s + 1);
+            const bool xf = chain && s + 1 < nsteps;
             float2 *S1 = c->at<float2>(c->o_S1);
             MM_TRY(timed(c, xf ? MM_K_XINV_LOCAL_XFWD : MM_K_XINV_LOCAL, "x-inverse + llg step", [&] {
-                return mmk::launch_xinv_euler(c->g, p, S1, src(s), h_map_ptr(c), (float)dt, renorm, dst(s), flag,
-                                              c->stream, xf ? S1 : nullptr);
+                return mmk::launch_xinv_euler(c->g, p, S1, src(s), ms_map_ptr(c), h_map_ptr(c), (float)dt, renorm,
+                                              dst(s), hs, flag, c->stream, xf ? S1 : nullptr);
             }));
             have_s1 = xf;
             continue;
@@ -1430,8 +1430,8 @@ std::vector<char> plan_image(const mm_batch *b, const float *m)
                         put(L.o_desc[0] + sizeof(zd) * k, &zd, sizeof(zd));
                     }
                 } else if (L.pass == 4) {
-                    const mmk::XeDesc xe{sm.g, b->at<float2>(sm.o_S1), src, nullptr, dst, nullptr,
-                                         (float)sm.h[0], (float)sm.h[1], (float)sm.h[2], 0};
+                    const mmk::XeDesc xe{sm.g,    b->at<float2>(sm.o_S1), src, nullptr, nullptr, dst, nullptr,
+                                         nullptr, (float)sm.h[0], (float)sm.h[1], (float)sm.h[2], 0};
                     put(L.o_desc[par] + sizeof(xe) * k, &xe, sizeof(xe));
                 } else {
                     mmk::LocalDesc ld{sm.g, src, b->at<float>(sm.o_S2), nullptr, nullptr, dst, nullptr,

@@ -1210,48 +1210,17 @@ struct XEShape {
     static_assert(LPB * L / 4 <= THREADS, "too few threads for the update");
 };
 
-template <int L, int LPB_, int V, bool TAB, bool XF>
-__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(PassArg<XeDesc, TAB> A, LocalParams p,
-                                                                           float dt, int renorm,
-                                                                           int *__restrict__ flag)
+// The front of the fused passes: the x-inverse of the block's tile (the
+// three components of LPB y-lines from y0, z-plane z) into LDS as
+// [3][LPB][nx] floats at sm.  `pre` runs once the tile's loads are issued
+// (the caller's own loads, which then complete under the transform).
+// Every thread of the block takes part; it ends with a barrier.
+template <int L, int LPB_, typename Pre>
+__device__ __forceinline__ void xe_front(const float2 *__restrict__ S1, const Geo &g, int z, int y0, int nl,
+                                         float2 *sm, Pre &&pre)
 {
     using S = XEShape<L, LPB_>;
-    constexpr int E = S::E, T = S::T, LPB = S::LPB, NL = S::NL, LD = S::LD, G = S::G;
-    extern __shared__ float2 sm[];
-    const XeDesc D = pass_desc(A);
-    const Geo &g = D.g;
-    const float2 *__restrict__ S1 = D.S1;
-    float hsc = 1.f;
-    if (p.sched) {  // time-dependent field, as in k_local's Euler step
-        const double t = p.clk[p.tslot];
-        hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
-    }
-    const int ntiles = (g.ny + LPB - 1) / LPB;
-    if constexpr (TAB) {
-        if ((long long)blockIdx.x >= (long long)g.nz * ntiles) return;  // block-uniform, before any barrier
-    }
-    int z, tile;
-    {
-        const int b = blockIdx.x, groups = ntiles / G;
-        if (ntiles % G == 0 && ((long long)g.nz * groups) % 8 == 0) {
-            const int P = 8 * (b / (8 * G)) + (b & 7);
-            z = P / groups;
-            tile = G * (P - z * groups) + (b / 8) % G;
-        } else {
-            z = b / ntiles;
-            tile = b - z * ntiles;
-        }
-    }
-    const LocalDesc DL{g, D.m, nullptr, nullptr, D.h_map, D.m_out, nullptr, D.h0, D.h1, D.h2};
-    const int y0 = tile * LPB;
-    const int nl = min(LPB, g.ny - y0);
-    // V = 4: this thread's update cells, 4 from (x0, y, z), if it has any
-    const int q4 = g.nx / 4;
-    const int w = threadIdx.x;
-    const int yl_u = V == 4 ? w / q4 : 0, x0 = V == 4 ? (w - yl_u * q4) * 4 : 0, y = y0 + yl_u;
-    const bool upd = V == 4 && w < LPB * q4 && y < g.ny;
-    const long long i0 = ((long long)z * g.ny + y) * g.nx + x0;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB, NL = S::NL, LD = S::LD;
     float2 *const tw = sm + NL * LD;
     load_half_twiddles<L, S::THREADS>(tw);
     // the three components' tiles, (L + 1) x NL entries, line r = c LPB + yl
@@ -1266,11 +1235,7 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
                          ? S1[(((long long)c * g.nz + z) * g.Hx + kx) * g.ny + y0 + yl]
                          : make_float2(0.f, 0.f);
     }
-    float mc[3][4];
-    if (upd) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) vload<4>(D.m + c * g.N + i0, mc[c]);
-    }
+    pre();
     const int ll = threadIdx.x / T, t = threadIdx.x - ll * T;
     TwSet<L, E> twl;
     load_twiddles<L, E>(twl, t);
@@ -1318,6 +1283,66 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
         }
     }
     __syncthreads();
+}
+
+// z-plane and y-tile of block b of a fused pass (the block order above)
+template <int LPB, int G>
+__device__ __forceinline__ void xe_tile(const Geo &g, int b, int &z, int &tile)
+{
+    const int ntiles = (g.ny + LPB - 1) / LPB, groups = ntiles / G;
+    if (ntiles % G == 0 && ((long long)g.nz * groups) % 8 == 0) {
+        const int P = 8 * (b / (8 * G)) + (b & 7);
+        z = P / groups;
+        tile = G * (P - z * groups) + (b / 8) % G;
+    } else {
+        z = b / ntiles;
+        tile = b - z * ntiles;
+    }
+}
+
+template <int L, int LPB_, int V, bool TAB, bool XF, bool MAPPED>
+__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(PassArg<XeDesc, TAB> A, LocalParams p,
+                                                                           float dt, int renorm,
+                                                                           int *__restrict__ flag)
+{
+    using S = XEShape<L, LPB_>;
+    constexpr int E = S::E, T = S::T, LPB = S::LPB, NL = S::NL, LD = S::LD, G = S::G;
+    extern __shared__ float2 sm[];
+    const XeDesc D = pass_desc(A);
+    const Geo &g = D.g;
+    const float2 *__restrict__ S1 = D.S1;
+    float hsc = 1.f;
+    if (p.sched) {  // time-dependent field, as in k_local's Euler step
+        const double t = p.clk[p.tslot];
+        hsc = (float)field_scale(t, p.t_start, p.t_decay, p.t_stop);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) p.clk[p.tslot ^ 1] = t + p.dt64;
+    }
+    const int ntiles = (g.ny + LPB - 1) / LPB;
+    if constexpr (TAB) {
+        if ((long long)blockIdx.x >= (long long)g.nz * ntiles) return;  // block-uniform, before any barrier
+    }
+    int z, tile;
+    xe_tile<LPB, G>(g, blockIdx.x, z, tile);
+    static_assert(!(XF && MAPPED), "the chained x-forward takes a uniform Ms");
+    const LocalDesc DL{g, D.m, nullptr, MAPPED ? D.ms_map : nullptr, D.h_map, D.m_out, nullptr, D.h0, D.h1, D.h2};
+    const int y0 = tile * LPB;
+    const int nl = min(LPB, g.ny - y0);
+    // V = 4: this thread's update cells, 4 from (x0, y, z), if it has any
+    const int q4 = g.nx / 4;
+    const int w = threadIdx.x;
+    const int yl_u = V == 4 ? w / q4 : 0, x0 = V == 4 ? (w - yl_u * q4) * 4 : 0, y = y0 + yl_u;
+    const bool upd = V == 4 && w < LPB * q4 && y < g.ny;
+    const long long i0 = ((long long)z * g.ny + y) * g.nx + x0;
+    float mc[3][4];
+    xe_front<L, LPB_>(S1, g, z, y0, nl, sm, [&] {
+        if (upd) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) vload<4>(D.m + c * g.N + i0, mc[c]);
+        }
+    });
+    float *const sH = reinterpret_cast<float *>(sm);
+    constexpr int NIT = ((L + 1) * NL + S::THREADS - 1) / S::THREADS;
+    float2 *const tw = sm + NL * LD;
     // XF: the next state of the tile's cells also goes to LDS ([3][LPB][nx]
     // floats after H_demag), for the next step's x-forward below
     float *const sM = sH + 3 * LPB * g.nx;
@@ -1331,10 +1356,11 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
                 h[c][1] = hv.y;
                 h[c][2] = hv.z;
                 h[c][3] = hv.w;
+                if (D.hd_out) vstore<4>(D.hd_out + c * g.N + i0, h[c]);
             }
             bool mag[4];
             float inv_ms[4];
-            local_field<4, false, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
+            local_field<4, MAPPED, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
             if constexpr (XF) {
                 float o[3][4];
                 bool bad = false;
@@ -1355,10 +1381,13 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
             const long long i = ((long long)z * g.ny + y0 + yl) * g.nx + x;
             float m1[3][1], h1[3][1];
 #pragma unroll
-            for (int c = 0; c < 3; ++c) h1[c][0] = sH[(c * LPB + yl) * g.nx + x];
+            for (int c = 0; c < 3; ++c) {
+                h1[c][0] = sH[(c * LPB + yl) * g.nx + x];
+                if (D.hd_out) D.hd_out[c * g.N + i] = h1[c][0];
+            }
             bool mag[1];
             float inv_ms[1];
-            local_field<1, false>(DL, p, 15u, hsc, i, x, y0 + yl, z, m1, h1, mag, inv_ms);
+            local_field<1, MAPPED>(DL, p, 15u, hsc, i, x, y0 + yl, z, m1, h1, mag, inv_ms);
             if constexpr (XF) {
                 float o[3][1];
                 bool bad = false;
@@ -1542,14 +1571,15 @@ __global__ __launch_bounds__(kThreads) void k_adj_a(Geo g, LocalParams p, const 
 }
 
 // lam = lam_loc + (2A/mu0) L(g_H/Ms) + Ms D,  dL/dMs += m.D,  D = -(N * g_H)
-__global__ __launch_bounds__(kThreads) void k_adj_b(Geo g, LocalParams p, const float *__restrict__ m,
-                                                    const float *__restrict__ gH, const float *__restrict__ D,
-                                                    const float *__restrict__ ms_map,
-                                                    const float *__restrict__ lam_loc, float *__restrict__ lam,
-                                                    float *__restrict__ g_ms)
+// The completion of one cell i = (x, y, z) of the adjoint step: lam = lam_loc
+// + (exchange transpose of g_H / Ms) + Ms d and g_ms += m.d, where d = (dx,
+// dy, dz) = -(N * g_H) at the cell (the demag pipeline's output for g_H
+// with unit Ms).
+__device__ __forceinline__ void adjb_cell(const Geo &g, const LocalParams &p, const float *__restrict__ m,
+                                          const float *__restrict__ gH, const float *__restrict__ ms_map,
+                                          const float *__restrict__ lam_loc, float *__restrict__ lam,
+                                          float *__restrict__ g_ms, long long i, float dx, float dy, float dz)
 {
-    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
-    if (i >= g.N) return;
     const long long N = g.N;
     const int x = (int)(i % g.nx);
     const long long r = i / g.nx;
@@ -1571,11 +1601,22 @@ __global__ __launch_bounds__(kThreads) void k_adj_b(Geo g, LocalParams p, const 
     if (y < g.ny - 1) add(i + sy, p.ay);
     if (z > 0) add(i - sz, p.az);
     if (z < g.nz - 1) add(i + sz, p.az);
-    const float dx = D[i], dy = D[N + i], dz = D[2 * N + i];
     lam[i] = lam_loc[i] + lx + ms * dx;
     lam[N + i] = lam_loc[N + i] + ly + ms * dy;
     lam[2 * N + i] = lam_loc[2 * N + i] + lz + ms * dz;
     if (g_ms) g_ms[i] += m[i] * dx + m[N + i] * dy + m[2 * N + i] * dz;
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_b(Geo g, LocalParams p, const float *__restrict__ m,
+                                                    const float *__restrict__ gH, const float *__restrict__ D,
+                                                    const float *__restrict__ ms_map,
+                                                    const float *__restrict__ lam_loc, float *__restrict__ lam,
+                                                    float *__restrict__ g_ms)
+{
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= g.N) return;
+    const long long N = g.N;
+    adjb_cell(g, p, m, gH, ms_map, lam_loc, lam, g_ms, i, D[i], D[N + i], D[2 * N + i]);
 }
 
 // ------------------------------------------------------------------------
@@ -2308,7 +2349,7 @@ long long xe_blocks(const Geo &g)
     return (long long)g.nz * ((g.ny + MMK_XE_LPB - 1) / MMK_XE_LPB);
 }
 
-template <bool TAB, bool XF>
+template <bool TAB, bool XF, bool MAPPED>
 static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px, bool vec, const LocalParams &p,
                                 float dt, int renorm, int *flag, hipStream_t s)
 {
@@ -2319,11 +2360,11 @@ static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px
             using S = XEShape<LL, MMK_XE_LPB>;                                                \
             const size_t lds = S::LDS * sizeof(float2);                                       \
             if (vec)                                                                          \
-                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 4, TAB, XF>), grid, dim3(S::THREADS), lds, s, a, p, \
-                           dt, renorm, flag);                                                 \
+                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 4, TAB, XF, MAPPED>), grid, dim3(S::THREADS), lds, \
+                           s, a, p, dt, renorm, flag);                                        \
             else                                                                              \
-                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 1, TAB, XF>), grid, dim3(S::THREADS), lds, s, a, p, \
-                           dt, renorm, flag);                                                 \
+                MMK_LAUNCH((k_xinv_euler<LL, MMK_XE_LPB, 1, TAB, XF, MAPPED>), grid, dim3(S::THREADS), lds, \
+                           s, a, p, dt, renorm, flag);                                        \
             return hipGetLastError();                                                         \
         }                                                                                     \
         break;                                                                                \
@@ -2337,21 +2378,23 @@ static hipError_t launch_xe_any(const PassArg<XeDesc, TAB> &a, dim3 grid, int Px
 }
 
 hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
-                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s,
-                             float2 *S1_next)
+                             const float *ms_map, const float *h_map, float dt, int renorm, float *out_m,
+                             float *hd_out, int *flag, hipStream_t s, float2 *S1_next)
 {
-    if (!fused_xinv_euler_ok(g) || (S1_next && S1_next != S1)) return hipErrorInvalidValue;
-    const PassArg<XeDesc, false> a{XeDesc{g, S1, m, h_map, out_m, S1_next, p.h0, p.h1, p.h2, 0}};
+    if (!fused_xinv_euler_ok(g) || (S1_next && (S1_next != S1 || ms_map))) return hipErrorInvalidValue;
+    const PassArg<XeDesc, false> a{XeDesc{g, S1, m, h_map, ms_map, out_m, S1_next, hd_out, p.h0, p.h1, p.h2, 0}};
     const dim3 grid((unsigned)xe_blocks(g));
-    if (S1_next) return launch_xe_any<false, true>(a, grid, g.Px, g.nx % 4 == 0, p, dt, renorm, flag, s);
-    return launch_xe_any<false, false>(a, grid, g.Px, g.nx % 4 == 0, p, dt, renorm, flag, s);
+    const bool vec = g.nx % 4 == 0;
+    if (S1_next) return launch_xe_any<false, true, false>(a, grid, g.Px, vec, p, dt, renorm, flag, s);
+    if (ms_map) return launch_xe_any<false, false, true>(a, grid, g.Px, vec, p, dt, renorm, flag, s);
+    return launch_xe_any<false, false, false>(a, grid, g.Px, vec, p, dt, renorm, flag, s);
 }
 
 hipError_t launch_xinv_euler_table(const Table<XeDesc> &t, int Px, bool vec, const LocalParams &p, float dt,
                                    int renorm, int *flag, hipStream_t s)
 {
     if (!table_ok(t)) return hipErrorInvalidValue;
-    return launch_xe_any<true, false>(targ(t), tgrid(t), Px, vec, p, dt, renorm, flag, s);
+    return launch_xe_any<true, false, false>(targ(t), tgrid(t), Px, vec, p, dt, renorm, flag, s);
 }
 
 struct OpMax {

@@ -83,9 +83,10 @@ struct LocalDesc {
 struct XeDesc {
     Geo g;
     const float2 *S1;
-    const float *m, *h_map;
+    const float *m, *h_map, *ms_map;
     float *m_out;
     float2 *S1w;
+    float *hd_out;     // H_demag of every cell, when not NULL
     float h0, h1, h2;  // uniform external field of this sample (no map)
     int pad;
 };
@@ -187,14 +188,16 @@ hipError_t launch_local(const Geo &g, const LocalParams &p, const float *m, cons
                         const float *ms_map, const float *h_map, uint32_t terms, int mode,
                         float dt, int renorm, float *out_m, float *out_h, int *flag, hipStream_t s);
 // a5-a8 in one launch: x-inverse of S1 (H_demag kept on chip) + local terms +
-// Euler step of m into out_m; for uniform Ms, 8 <= Px <= 512 and nx <= Px/2
+// Euler step of m into out_m; for 8 <= Px <= 512 and nx <= Px/2
 // (fused_xinv_euler_ok)
 bool fused_xinv_euler_ok(const Geo &g);
-// S1_next != NULL: the launch also runs the next step's x-forward of out_m
-// (as launch_xfwd with Ms = p.ms) into S1_next, which must be S1 itself
+// ms_map: per-cell Ms (vacuum where 0) or NULL; hd_out != NULL also stores
+// H_demag of every cell there.  S1_next != NULL (uniform Ms only): the
+// launch also runs the next step's x-forward of out_m (as launch_xfwd with
+// Ms = p.ms) into S1_next, which must be S1 itself
 hipError_t launch_xinv_euler(const Geo &g, const LocalParams &p, const float2 *S1, const float *m,
-                             const float *h_map, float dt, int renorm, float *out_m, int *flag, hipStream_t s,
-                             float2 *S1_next = nullptr);
+                             const float *ms_map, const float *h_map, float dt, int renorm, float *out_m,
+                             float *hd_out, int *flag, hipStream_t s, float2 *S1_next = nullptr);
 // the same for many samples of one padded x length Px and one update width
 // (vec: nx % 4 == 0); every sample fused_xinv_euler_ok
 hipError_t launch_xinv_euler_table(const Table<XeDesc> &t, int Px, bool vec, const LocalParams &p, float dt,

@@ -167,3 +167,75 @@ def test_batch_fused_equals_two_kernel_steps(gpu_lib):
         assert torch.equal(a, b)
         assert torch.equal(c, d)
         B.close()
+
+
+@pytest.mark.parametrize("vacuum", [False, True], ids=["ms-map", "vacuum"])
+@pytest.mark.parametrize("n", [(32, 20, 3), (30, 17, 2)], ids=lambda n: "x".join(map(str, n)))
+def test_fused_step_with_ms_map(gpu_lib, n, vacuum):
+    """An Ms map (with vacuum cells: a disk) takes the mapped fused pass:
+    equal bit for bit to the two-kernel step at every fusion level."""
+    import torch
+    rng = np.random.default_rng(12)
+    nx, ny, nz = n
+    ms = 8e5 * (1.0 + 0.2 * rng.random((nz, ny, nx)))
+    if vacuum:
+        yy, xx = np.mgrid[0:ny, 0:nx]
+        ms[:, (xx - nx / 2 + 0.5) ** 2 + (yy - ny / 2 + 0.5) ** 2 > (0.45 * min(nx, ny)) ** 2] = 0.0
+    m0 = workloads.sphere(rng, (3, nz, ny, nx))
+    out = []
+    for level in (0, 1, 2):
+        sim = gpu_lib.Sim(n, (4e-9, 4e-9, 3e-9), Ms=8e5, A=1.3e-11, Ku=2e4, u=(0.0, 0.0, 1.0), alpha=0.2,
+                          hext=(1e4, 2e4, -1e4))
+        msg = gpu(ms)
+        gpu_lib.mm_set_ms_map(sim.ctx, msg, sim.N)
+        gpu_lib.mm_set_fusion(sim.ctx, level)
+        m = gpu(m0)
+        gpu_lib.mm_kernel_timing(sim.ctx, True)
+        sim.step(m, 6, 2e-14)
+        t = gpu_lib.mm_kernel_times(sim.ctx)
+        gpu_lib.mm_kernel_timing(sim.ctx, False)
+        sim.sync()
+        out.append((m, t))
+        sim.close()
+        del msg
+    assert torch.isfinite(out[0][0]).all()
+    assert torch.equal(out[1][0], out[0][0]) and torch.equal(out[2][0], out[0][0])
+    # with a map, level 2 runs as level 1 (the chained x-forward needs a uniform Ms)
+    assert out[1][1]["xinv_local"][1] == 6 and out[2][1]["xinv_local"][1] == 6
+    assert out[2][1]["xinv_local_xfwd"][1] == 0 and out[0][1]["local"][1] == 6
+
+
+def test_fused_forward_store_and_adjoint(gpu_lib):
+    """mm_forward_store (states and H_demag of every step) and the adjoint
+    segment with the fused x-inverse passes equal the two-kernel forms bit
+    for bit, with Ms and field maps."""
+    import torch
+    n = (24, 20, 4)
+    rng = np.random.default_rng(13)
+    N = n[0] * n[1] * n[2]
+    ms = 8e5 * (1.0 + 0.1 * rng.random((n[2], n[1], n[0])))
+    hm = 2e4 * rng.standard_normal((3, n[2], n[1], n[0]))
+    m0 = workloads.sphere(rng, (3, n[2], n[1], n[0]))
+    lam0 = rng.standard_normal((3, N))
+    res = []
+    for level in (0, 1):
+        sim = gpu_lib.Sim(n, (5e-9,) * 3, Ms=8e5, A=1.3e-11, alpha=0.1)
+        msg, hmg = gpu(ms), gpu(hm)
+        gpu_lib.mm_set_ms_map(sim.ctx, msg, N)
+        gpu_lib.mm_set_hext_map(sim.ctx, hmg, N)
+        gpu_lib.mm_set_fusion(sim.ctx, level)
+        m = gpu(m0)
+        mt = torch.empty((7, 3 * N), dtype=torch.float32, device="cuda:0")
+        ht = torch.empty_like(mt)
+        gpu_lib.mm_forward_store(sim.ctx, m, 7, 2e-14, 0, mt, ht, N)
+        lam = gpu(lam0)
+        g_h = torch.zeros_like(hmg)
+        g_ms = torch.zeros_like(msg)
+        gpu_lib.mm_adjoint_segment(sim.ctx, mt, ht, 7, lam, g_h, g_ms, 2e-14, 0, N)
+        sim.sync()
+        res.append((m, mt, ht, lam, g_h, g_ms))
+        sim.close()
+        del msg, hmg
+    for a, b in zip(*res):
+        assert torch.isfinite(a).all()
+        assert torch.equal(a, b)
