@@ -384,7 +384,7 @@ def small_configs(binding):
     return rows
 
 
-def sweep_row(binding, w):
+def sweep_row(binding, w, graphs=True):
     import torch
     from paper_1411_2565_amd import workloads
     m0, _ = workloads.inputs(w)
@@ -394,10 +394,11 @@ def sweep_row(binding, w):
     t_build = time.perf_counter() - t
     m = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
     steps = 32 * max(4, min(64, int(6e7 / w.N)))
-    sim.step(m, 64, w.dt, binding.MM_F_GRAPH)
+    if graphs:
+        sim.step(m, 64, w.dt, binding.MM_F_GRAPH)
     sim.step(m, 32, w.dt)
     te = timed_steps(sim, m, steps, w.dt, 0)
-    tg = timed_steps(sim, m, steps, w.dt, binding.MM_F_GRAPH)
+    tg = timed_steps(sim, m, steps, w.dt, binding.MM_F_GRAPH) if graphs else None
     binding.mm_kernel_timing(sim.ctx, True)
     sim.step(m, 20, w.dt)
     kt = binding.mm_kernel_times(sim.ctx)
@@ -406,13 +407,14 @@ def sweep_row(binding, w):
     sim.close()
     N = w.n[0]
     return {"n": N, "cells": w.N, "padded": [padded(v) for v in w.n], "steps": steps,
-            "us_per_step": round(1e6 * te / steps, 2), "us_per_step_graph": round(1e6 * tg / steps, 2),
-            "cell_steps_per_s": w.N * steps / min(te, tg), "tensor_build_s": round(t_build, 3),
+            "us_per_step": round(1e6 * te / steps, 2),
+            "us_per_step_graph": round(1e6 * tg / steps, 2) if graphs else None,
+            "cell_steps_per_s": w.N * steps / (min(te, tg) if graphs else te), "tensor_build_s": round(t_build, 3),
             "kernels_us": {k: round(1e3 * t / c, 2) for k, (t, c) in kt.items() if c},
             "paper_ms_per_step": PAPER_TABLE1_MS.get(N)}
 
 
-def size_sweep(binding, sizes=None):
+def size_sweep(binding, sizes=None, graphs=True):
     """Per-step time on Table 1's N^3 cubes (A = 1e-11 J/m, Ms = 1e6 A/m,
     anisotropy field 1e5 A/m along x, 5 nm cells, alpha = 0.5, dt = 1e-13 s,
     random initial state): eager launches and 32-step hipGraph chunks."""
@@ -422,7 +424,7 @@ def size_sweep(binding, sizes=None):
     s = torch.cuda.Stream()  # graph capture needs a non-default stream
     for N in sizes or workloads.TABLE1_SIZES:
         with torch.cuda.stream(s):
-            rows.append(sweep_row(binding, workloads.table1_cube(N)))
+            rows.append(sweep_row(binding, workloads.table1_cube(N), graphs))
         torch.cuda.empty_cache()
     return {"workload": "N^3 cubes, 5 nm cells, A=1e-11, Ms=1e6, H_K=1e5 A/m along x, alpha=0.5, dt=1e-13",
             "paper_hardware": "AMD Radeon HD 7970 GHz Edition (Table 1)", "rows": rows}
@@ -559,6 +561,8 @@ def main():
                     help="skip the plain-vs-compensated timing and crop errors")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-films throughput")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="with --sweep: time the cubes with eager launches only (for rocprofv3 --pmc runs)")
     ap.add_argument("--no-small", action="store_true",
                     help="skip the latency-bound workloads (they replay hipGraphs, which rocprofv3 --pmc "
                          "runs of this ROCm have not survived)")
@@ -665,7 +669,7 @@ def main():
     sweep = sp4 = None
     if args.sweep:
         print("bench: N^3 cube size sweep", file=sys.stderr, flush=True)
-        sweep = size_sweep(binding, args.sweep_sizes)
+        sweep = size_sweep(binding, args.sweep_sizes, graphs=not args.no_graphs)
         if not args.sweep_sizes:
             print("bench: standard problem #4 film", file=sys.stderr, flush=True)
             sp4 = sp4_rate(binding)
