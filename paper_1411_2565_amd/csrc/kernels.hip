@@ -607,9 +607,9 @@ __device__ __forceinline__ int zc_tile_seq(int slot, int ntiles, int G)
 // a barrier after its reads, so the next one's first writes cannot overtake
 // them).  Each component is stored as soon as its inverse transform ends.
 // Blocks of MMK_ZC_SEQ_THREADS threads held to MMK_ZC_SEQ_WAVES waves per
-// SIMD: the form needs 164-173 VGPRs, and at 256^3 (512-point columns) 3
-// waves per SIMD (168 VGPRs, 3 spilled) ran the pass in 767 us against 910
-// us at 2; 4 waves spill 60-90 registers.
+// SIMD: the form needs 160-168 VGPRs, and at 256^3 (512-point columns) 3
+// waves per SIMD ran the pass in 718 us against 910 us at 2; at 4 the
+// compiler spills 62-82 registers.
 template <int L, bool COMP, int V, bool TAB>
 __global__ __launch_bounds__((ZShape<L, V>::THREADS)) MMK_ZC_SEQ_ATTR void k_zconv_seq(PassArg<ZDesc, TAB> A)
 {
@@ -665,15 +665,19 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) MMK_ZC_SEQ_ATTR void k_zco
     const float *kcol = D.K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
 #pragma unroll
     for (int q = 0; q < E; ++q) zc_point<COMP>(v[0][q], v[1][q], v[2][q], kcol, ok, t + q * T, g.Pz, sy);
-    // store addresses computed afresh rather than kept from the loads
+    // store addresses and z indices computed afresh rather than kept from
+    // the loads (held over the six transforms, the z indices of a 512-point
+    // column were spilled to scratch memory)
     asm volatile("" : "+v"(base));
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         fft(std::true_type{}, c);
         if (ok) {
+            int ts = t;
+            asm volatile("" : "+v"(ts));
 #pragma unroll
             for (int q = 0; q < H; ++q) {
-                const int zz = t + q * T;
+                const int zz = ts + q * T;
                 if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
             }
         }
@@ -1185,10 +1189,14 @@ __global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, L
 //   step bit for bit.
 // TAB: many samples, one per blockIdx.y (descriptors in device memory).
 // Block order: G = 16/LPB tiles share the 128-byte lines of S1 (runs of LPB
-// complex values).  Block b = 8 G K + 8 h + x (x the XCD) takes tile G P + h
-// of the tile group P = 8 K + x, so the tiles of a group run back to back on
-// one XCD, and each XCD keeps the same y-tiles in every z-plane (the
-// z-neighbour rows of its cells stay in its L2).
+// complex values).  Block b = 8 G K + 8 h + x (x the XCD) takes tile h of
+// group P = 8 K + x, so the tiles of a group run back to back on one XCD, and
+// each XCD keeps the same y-tiles in every z-plane (the z-neighbour rows of
+// its cells stay in its L2).  When a plane has a multiple of 8 groups, the
+// XCD's groups of a plane are adjacent (one y-range), so the y-neighbour rows
+// at the edges between them are read once: measured on the 256x256x32 block,
+// the pass fetched 79.5 MB against 81.5 MB with the groups 8 apart, at the
+// same time within noise.
 // ------------------------------------------------------------------------
 #ifndef MMK_XE_LPB
 #define MMK_XE_LPB 8
@@ -1293,7 +1301,12 @@ __device__ __forceinline__ void xe_tile(const Geo &g, int b, int &z, int &tile)
     if (ntiles % G == 0 && ((long long)g.nz * groups) % 8 == 0) {
         const int P = 8 * (b / (8 * G)) + (b & 7);
         z = P / groups;
-        tile = G * (P - z * groups) + (b / 8) % G;
+        int gi = P - z * groups;
+        if (groups % 8 == 0) {  // the XCD's groups of a plane: one y-range
+            const int r = groups / 8;
+            gi = (gi & 7) * r + (gi >> 3);
+        }
+        tile = G * gi + (b / 8) % G;
     } else {
         z = b / ntiles;
         tile = b - z * ntiles;
