@@ -485,25 +485,28 @@ __device__ __forceinline__ int zc_tile(int slot, int ntiles)
 }
 
 // H(k) = K(k) M(k) at one frequency kz of a column: the octant entries
-// K[kx][kyf][kzf] (6 floats: xx yy zz xy xz yz) with the signs of the
-// mirrored axes (N_xy odd in ky, N_xz in kz, N_yz in both).  ok = false (a
-// column beyond Py) multiplies by zero.
-template <bool COMP>
-__device__ __forceinline__ void zc_point(float2 &mx, float2 &my, float2 &mz, const float *kcol, bool ok, int kz,
-                                         int Pz, float sy)
+// K[kx][kyf][kzf] (6 floats: xx yy zz xy xz yz; zc_kload) with the signs of
+// the mirrored axes (N_xy odd in ky, N_xz in kz, N_yz in both; zc_apply).
+// ok = false (a column beyond Py) multiplies by zero.
+__device__ __forceinline__ void zc_kload(float2 (&k)[3], const float *kcol, bool ok, int kz, int Pz)
 {
-    const bool fz = kz > Pz / 2;
-    const int kzf = fz ? Pz - kz : kz;
-    const float sz = fz ? -1.f : 1.f;
-    float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
+    const int kzf = kz > Pz / 2 ? Pz - kz : kz;
+    k[0] = k[1] = k[2] = make_float2(0.f, 0.f);
     if (ok) {
         const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
-        k01 = kp[0];
-        k23 = kp[1];
-        k45 = kp[2];
+        k[0] = kp[0];
+        k[1] = kp[1];
+        k[2] = kp[2];
     }
-    const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
-    const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
+}
+
+template <bool COMP>
+__device__ __forceinline__ void zc_apply(float2 &mx, float2 &my, float2 &mz, const float2 (&k)[3], int kz, int Pz,
+                                         float sy)
+{
+    const float sz = kz > Pz / 2 ? -1.f : 1.f;
+    const float kxx = k[0].x, kyy = k[0].y, kzz = k[1].x;
+    const float kxy = sy * k[1].y, kxz = sz * k[2].x, kyz = sy * sz * k[2].y;
     const float2 ax = mx, ay = my, az = mz;
     if (COMP) {
         mx = make_float2(dot3_comp(kxx, ax.x, kxy, ay.x, kxz, az.x), dot3_comp(kxx, ax.y, kxy, ay.y, kxz, az.y));
@@ -514,6 +517,15 @@ __device__ __forceinline__ void zc_point(float2 &mx, float2 &my, float2 &mz, con
         my = make_float2(fmaf(kxy, ax.x, fmaf(kyy, ay.x, kyz * az.x)), fmaf(kxy, ax.y, fmaf(kyy, ay.y, kyz * az.y)));
         mz = make_float2(fmaf(kxz, ax.x, fmaf(kyz, ay.x, kzz * az.x)), fmaf(kxz, ax.y, fmaf(kyz, ay.y, kzz * az.y)));
     }
+}
+
+template <bool COMP>
+__device__ __forceinline__ void zc_point(float2 &mx, float2 &my, float2 &mz, const float *kcol, bool ok, int kz,
+                                         int Pz, float sy)
+{
+    float2 k[3];
+    zc_kload(k, kcol, ok, kz, Pz);
+    zc_apply<COMP>(mx, my, mz, k, kz, Pz, sy);
 }
 
 template <int L, bool COMP, int V, bool TAB>
@@ -568,13 +580,18 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc
         const bool fy = ky > hy;
         const int kyf = fy ? g.Py - ky : ky;
         const float sy = fy ? -1.f : 1.f;
-        // this column's octant entries: K[kx][kyf][kz][6], contiguous over kz
+        // this column's octant entries: K[kx][kyf][kz][6], contiguous over kz,
+        // loaded with the data, so that they arrive under the forward
+        // transform (left to the compiler, they were loaded after it)
         const float *kcol = K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
+        float2 kk[E][3];
+#pragma unroll
+        for (int q = 0; q < E; ++q) zc_kload(kk[q], kcol, ok, t + q * T, g.Pz);
         float2 *const lds[3] = {sm + (0 * CB + col) * lds_line(L), sm + (1 * CB + col) * lds_line(L),
                                 sm + (2 * CB + col) * lds_line(L)};
         reg_fft<L, false>(v, lds, t, tw);
 #pragma unroll
-        for (int q = 0; q < E; ++q) zc_point<COMP>(v[0][q], v[1][q], v[2][q], kcol, ok, t + q * T, g.Pz, sy);
+        for (int q = 0; q < E; ++q) zc_apply<COMP>(v[0][q], v[1][q], v[2][q], kk[q], t + q * T, g.Pz, sy);
         reg_fft<L, true>(v, lds, t, tw);
         if (ok) {
 #pragma unroll
