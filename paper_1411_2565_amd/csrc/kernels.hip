@@ -519,13 +519,36 @@ __device__ __forceinline__ void zc_apply(float2 &mx, float2 &my, float2 &mz, con
     }
 }
 
+// Both steps at one point, for the long transforms (k_zconv_seq), whose
+// register allocation is at its limit: written out in one piece, as the
+// composition of the two helpers above allocated 2 VGPRs more and spilled
+// them at 512 points.
 template <bool COMP>
 __device__ __forceinline__ void zc_point(float2 &mx, float2 &my, float2 &mz, const float *kcol, bool ok, int kz,
                                          int Pz, float sy)
 {
-    float2 k[3];
-    zc_kload(k, kcol, ok, kz, Pz);
-    zc_apply<COMP>(mx, my, mz, k, kz, Pz, sy);
+    const bool fz = kz > Pz / 2;
+    const int kzf = fz ? Pz - kz : kz;
+    const float sz = fz ? -1.f : 1.f;
+    float2 k01 = make_float2(0.f, 0.f), k23 = k01, k45 = k01;
+    if (ok) {
+        const float2 *kp = reinterpret_cast<const float2 *>(kcol + kzf * 6);
+        k01 = kp[0];
+        k23 = kp[1];
+        k45 = kp[2];
+    }
+    const float kxx = k01.x, kyy = k01.y, kzz = k23.x;
+    const float kxy = sy * k23.y, kxz = sz * k45.x, kyz = sy * sz * k45.y;
+    const float2 ax = mx, ay = my, az = mz;
+    if (COMP) {
+        mx = make_float2(dot3_comp(kxx, ax.x, kxy, ay.x, kxz, az.x), dot3_comp(kxx, ax.y, kxy, ay.y, kxz, az.y));
+        my = make_float2(dot3_comp(kxy, ax.x, kyy, ay.x, kyz, az.x), dot3_comp(kxy, ax.y, kyy, ay.y, kyz, az.y));
+        mz = make_float2(dot3_comp(kxz, ax.x, kyz, ay.x, kzz, az.x), dot3_comp(kxz, ax.y, kyz, ay.y, kzz, az.y));
+    } else {
+        mx = make_float2(fmaf(kxx, ax.x, fmaf(kxy, ay.x, kxz * az.x)), fmaf(kxx, ax.y, fmaf(kxy, ay.y, kxz * az.y)));
+        my = make_float2(fmaf(kxy, ax.x, fmaf(kyy, ay.x, kyz * az.x)), fmaf(kxy, ax.y, fmaf(kyy, ay.y, kyz * az.y)));
+        mz = make_float2(fmaf(kxz, ax.x, fmaf(kyz, ay.x, kzz * az.x)), fmaf(kxz, ax.y, fmaf(kyz, ay.y, kzz * az.y)));
+    }
 }
 
 template <int L, bool COMP, int V, bool TAB>
