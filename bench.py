@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel code whose hash
 # (kernel_source_sha) is recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 680.5 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258098176,
-              "source_sha": "3213178e7218d056c2e238d311d07d5adde6d05ac47642ec63064f1f5946f8e3"},
+    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 676.5 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258090048,
+              "source_sha": "2765fdddc4f89c31ddd942d1e962440aa35c83ed2983d417bb617b54670684bd"},
 }
 
 def kernel_source_sha():
