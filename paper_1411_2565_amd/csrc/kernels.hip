@@ -879,11 +879,26 @@ static int local_perm_q(const Geo &g, long long cells, long long nb)
 // holds H_demag (or zeros) on entry.  mag / inv_ms: magnetic cell, 1/Ms.
 // MAPPED: the sample carries an Ms map (per-cell Ms, and vacuum where it is
 // 0); without one this compiles to the uniform-Ms code alone.
-template <int V, bool MAPPED, bool LOADED = false>
+// TILE (uniform Ms only): m of the caller's y-lines y - yl ... y - yl + nl - 1
+// of this z-plane is also in LDS at st ([3][lpb][nx] floats), and the x and
+// y neighbours inside it are read from there; the z neighbours come in zn,
+// loaded by the caller.  The values are those the loads from m would
+// return, taken in the same order, so the field is the same bit for bit.
+// The z neighbours of V cells (the cells themselves where there is none),
+// loaded by the caller ahead of their use (TILE).
+template <int V>
+struct ZNeighbours {
+    float lo[3][V], hi[3][V];
+};
+
+template <int V, bool MAPPED, bool LOADED = false, bool TILE = false>
 __device__ __forceinline__ void local_field(const LocalDesc &D, const LocalParams &p, uint32_t terms, float hsc,
                                             long long i0, int x0, int y, int z, float (&mc)[3][V],
-                                            float (&h)[3][V], bool (&mag)[V], float (&inv_ms)[V])
+                                            float (&h)[3][V], bool (&mag)[V], float (&inv_ms)[V],
+                                            const float *st = nullptr, int yl = 0, int nl = 0, int lpb = 0,
+                                            const ZNeighbours<V> *zn = nullptr)
 {
+    static_assert(!(TILE && MAPPED), "the LDS tile path takes a uniform Ms");
     const Geo &g = D.g;
     const long long N = g.N;
     const float *__restrict__ m = D.m;
@@ -930,8 +945,15 @@ __device__ __forceinline__ void local_field(const LocalDesc &D, const LocalParam
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const float left = m[c * N + il];
-            const float right = m[c * N + ir];
+            float left, right;
+            if constexpr (TILE) {
+                const float *row = st + (c * lpb + yl) * g.nx;
+                left = row[gl ? x0 - 1 : x0];
+                right = row[gr ? x0 + V : x0 + V - 1];
+            } else {
+                left = m[c * N + il];
+                right = m[c * N + ir];
+            }
 #pragma unroll
             for (int j = 0; j < V; ++j) {
                 const float a = mc[c][j];
@@ -970,10 +992,45 @@ __device__ __forceinline__ void local_field(const LocalDesc &D, const LocalParam
                     if (nbm[j]) lap[c][j] = fmaf(w, nb[j] - mc[c][j], lap[c][j]);
             }
         };
-        add(y > 0 ? -sy : 0, p.ay);
-        add(y < g.ny - 1 ? sy : 0, p.ay);
-        add(z > 0 ? -sz : 0, p.az);
-        add(z < g.nz - 1 ? sz : 0, p.az);
+        if constexpr (TILE) {
+            // row yl + dy of the tile, or this row where there is no
+            // neighbour; rows beyond the tile from m
+            auto add_y = [&](bool has, int dy) {
+                const int yt = has ? yl + dy : yl;
+                if (yt < 0 || yt >= nl) {
+                    add(dy * sy, p.ay);
+                    return;
+                }
+                // an LDS-typed pointer, so that the compiler cannot merge
+                // this read and the load from m into one flat load
+                typedef __attribute__((address_space(3))) const float lds_float;
+                const lds_float *sl = (const lds_float *)st;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                    for (int j = 0; j < V; ++j)
+                        lap[c][j] = fmaf(p.ay, sl[(c * lpb + yt) * g.nx + x0 + j] - mc[c][j], lap[c][j]);
+                }
+            };
+            add_y(y > 0, -1);
+            add_y(y < g.ny - 1, 1);
+        } else {
+            add(y > 0 ? -sy : 0, p.ay);
+            add(y < g.ny - 1 ? sy : 0, p.ay);
+        }
+        if constexpr (TILE) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < V; ++j) lap[c][j] = fmaf(p.az, zn->lo[c][j] - mc[c][j], lap[c][j]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int j = 0; j < V; ++j) lap[c][j] = fmaf(p.az, zn->hi[c][j] - mc[c][j], lap[c][j]);
+        } else {
+            add(z > 0 ? -sz : 0, p.az);
+            add(z < g.nz - 1 ? sz : 0, p.az);
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -1241,6 +1298,10 @@ __global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, L
 #ifndef MMK_XE_LPB
 #define MMK_XE_LPB 8
 #endif
+// The uniform-Ms form without the chained x-forward, for lines of 128
+// points and more, is held to 6 waves per SIMD (80 VGPRs), so that two
+// 768-thread blocks share a CU.
+#define MMK_XE_ATTR(L, XF, MAPPED) __attribute__((amdgpu_waves_per_eu((!(MAPPED) && !(XF) && (L) >= 128) ? 6 : 1)))
 
 template <int L, int LPB_>
 struct XEShape {
@@ -1354,7 +1415,7 @@ __device__ __forceinline__ void xe_tile(const Geo &g, int b, int &z, int &tile)
 }
 
 template <int L, int LPB_, int V, bool TAB, bool XF, bool MAPPED>
-__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(PassArg<XeDesc, TAB> A, LocalParams p,
+__global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) MMK_XE_ATTR(L, XF, MAPPED) void k_xinv_euler(PassArg<XeDesc, TAB> A, LocalParams p,
                                                                            float dt, int renorm,
                                                                            int *__restrict__ flag)
 {
@@ -1396,10 +1457,34 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
     float *const sH = reinterpret_cast<float *>(sm);
     constexpr int NIT = ((L + 1) * NL + S::THREADS - 1) / S::THREADS;
     float2 *const tw = sm + NL * LD;
-    // XF: the next state of the tile's cells also goes to LDS ([3][LPB][nx]
-    // floats after H_demag), for the next step's x-forward below
+    // [3][LPB][nx] floats after H_demag: with XF the next state of the
+    // tile's cells, for the next step's x-forward below; otherwise, with a
+    // uniform Ms, the tile's present state, for the neighbours of the update
     float *const sM = sH + 3 * LPB * g.nx;
     if constexpr (V == 4) {
+        // uniform Ms without the chained x-forward: the tile's m also goes
+        // to LDS, where the x and y neighbours inside the tile are read
+        // instead of from m (with XF the form took 88 VGPRs against 82)
+        constexpr bool TILE = !MAPPED && !XF;
+        ZNeighbours<4> zn;
+        if constexpr (TILE) {
+            if (upd) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    *reinterpret_cast<float4 *>(sM + (c * LPB + yl_u) * g.nx + x0) =
+                        make_float4(mc[c][0], mc[c][1], mc[c][2], mc[c][3]);
+                // the z neighbours, issued before the barrier so that they
+                // arrive while the tile is read
+                const long long sz = (long long)g.nx * g.ny;
+                const long long lo = z > 0 ? -sz : 0, hi = z < g.nz - 1 ? sz : 0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) vload<4>(D.m + c * g.N + i0 + lo, zn.lo[c]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) vload<4>(D.m + c * g.N + i0 + hi, zn.hi[c]);
+            }
+            __syncthreads();
+        }
+        float o[3][4];  // XF: the next state, for the LDS tile below
         if (upd) {
             float h[3][4];
 #pragma unroll
@@ -1413,19 +1498,23 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) void k_xinv_euler(Pass
             }
             bool mag[4];
             float inv_ms[4];
-            local_field<4, MAPPED, true>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms);
+            local_field<4, MAPPED, true, TILE>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms, sM, yl_u, nl,
+                                               LPB, &zn);
             if constexpr (XF) {
-                float o[3][4];
                 bool bad = false;
                 euler_next<4>(p, dt, renorm, mc, h, mag, o, bad);
                 if (bad) *flag = 1;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    vstore<4>(D.m_out + c * g.N + i0, o[c]);
-                    vstore<4>(sM + (c * LPB + yl_u) * g.nx + x0, o[c]);
-                }
+                for (int c = 0; c < 3; ++c) vstore<4>(D.m_out + c * g.N + i0, o[c]);
             } else {
                 euler_store<4>(p, dt, renorm, mc, h, mag, D.m_out, g.N, i0, flag);
+            }
+        }
+        if constexpr (XF) {
+            if constexpr (TILE) __syncthreads();  // every thread has read the present state from the tile
+            if (upd) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) vstore<4>(sM + (c * LPB + yl_u) * g.nx + x0, o[c]);
             }
         }
     } else {
