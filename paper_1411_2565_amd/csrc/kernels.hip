@@ -1298,10 +1298,11 @@ __global__ __launch_bounds__(kThreads) void k_local(PassArg<LocalDesc, TAB> A, L
 #ifndef MMK_XE_LPB
 #define MMK_XE_LPB 8
 #endif
-// The uniform-Ms form without the chained x-forward, for lines of 128
-// points and more, is held to 6 waves per SIMD (80 VGPRs), so that two
-// 768-thread blocks share a CU.
-#define MMK_XE_ATTR(L, XF, MAPPED) __attribute__((amdgpu_waves_per_eu((!(MAPPED) && !(XF) && (L) >= 128) ? 6 : 1)))
+// The uniform-Ms forms, for lines of 128 points and more, are held to 6
+// waves per SIMD (80 VGPRs), so that two 768-thread blocks share a CU.  The
+// chained form then spills 3 VGPRs, but left at its 82 it ran one block per
+// CU: 57.0 us against 44.0 us on the 256x256x32 block.
+#define MMK_XE_ATTR(L, XF, MAPPED) __attribute__((amdgpu_waves_per_eu((!(MAPPED) && (L) >= 128) ? 6 : 1)))
 
 template <int L, int LPB_>
 struct XEShape {
@@ -1484,7 +1485,6 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) MMK_XE_ATTR(L, XF, MAP
             }
             __syncthreads();
         }
-        float o[3][4];  // XF: the next state, for the LDS tile below
         if (upd) {
             float h[3][4];
 #pragma unroll
@@ -1501,20 +1501,17 @@ __global__ __launch_bounds__((XEShape<L, LPB_>::THREADS)) MMK_XE_ATTR(L, XF, MAP
             local_field<4, MAPPED, true, TILE>(DL, p, 15u, hsc, i0, x0, y, z, mc, h, mag, inv_ms, sM, yl_u, nl,
                                                LPB, &zn);
             if constexpr (XF) {
+                float o[3][4];
                 bool bad = false;
                 euler_next<4>(p, dt, renorm, mc, h, mag, o, bad);
                 if (bad) *flag = 1;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) vstore<4>(D.m_out + c * g.N + i0, o[c]);
+                for (int c = 0; c < 3; ++c) {
+                    vstore<4>(D.m_out + c * g.N + i0, o[c]);
+                    vstore<4>(sM + (c * LPB + yl_u) * g.nx + x0, o[c]);
+                }
             } else {
                 euler_store<4>(p, dt, renorm, mc, h, mag, D.m_out, g.N, i0, flag);
-            }
-        }
-        if constexpr (XF) {
-            if constexpr (TILE) __syncthreads();  // every thread has read the present state from the tile
-            if (upd) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) vstore<4>(sM + (c * LPB + yl_u) * g.nx + x0, o[c]);
             }
         }
     } else {
