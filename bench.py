@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel code whose hash
 # (kernel_source_sha) is recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 676.5 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258090048,
-              "source_sha": "2765fdddc4f89c31ddd942d1e962440aa35c83ed2983d417bb617b54670684bd"},
+    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 676.4 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258089792,
+              "source_sha": "02c64c3d9e41417f2c0cfdff71b2350c3c627a4d3efbe17228ea866eddb5fca0"},
 }
 
 def kernel_source_sha():
