@@ -628,6 +628,150 @@ __global__ __launch_bounds__((ZShape<L, V>::THREADS)) void k_zconv(PassArg<ZDesc
     }
 }
 
+// The z pass for 64-point transforms (the default shape for Pz = 64).  A
+// block takes 16 adjacent ky columns; thread (col, r, w), lane 16 r + col of
+// wavefront w, holds the points z = t + 16 q, q = 0..3, of column col, with
+// t = 4 r + w.  Each component's forward transform is three radix-4 steps
+// in decimation in frequency, with z = 16 n2 + 4 n1 + n0 and the frequency
+// kz = k0 + 4 k1 + 16 k2, W = exp(-2 pi i / 64):
+//   1. over n2 = q in registers -> k0; times W^(t k0);
+//   2. the four rows of the wavefront (n1 = r) and the four registers (k0)
+//      are transposed with permlane swaps, so that row r holds k0 = r;
+//      over n1 in registers -> k1; times W^(4 n0 k1), n0 = w;
+//   3. one LDS exchange: thread (r, w) takes k0 = r, k1 = w from the four
+//      wavefronts n0; over n0 in registers -> k2.
+// The tensor multiply takes register k2 at kz = r + 4 w + 16 k2 (left in
+// this order), and the inverse runs the steps backwards with conjugate
+// twiddles (unnormalised, as the other z passes).  One LDS exchange per
+// transform instead of two, and three block barriers instead of eight.
+__device__ __forceinline__ void pl32_swap(float2 &a, float2 &b)
+{
+    const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+    b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+}
+__device__ __forceinline__ void pl16_swap(float2 &a, float2 &b)
+{
+    const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    a = make_float2(__uint_as_float(x[0]), __uint_as_float(y[0]));
+    b = make_float2(__uint_as_float(x[1]), __uint_as_float(y[1]));
+}
+// register j of row r <- register r of row j (rows of 16 lanes)
+__device__ __forceinline__ void rows_transpose4(float2 (&v)[4])
+{
+    pl32_swap(v[0], v[2]);
+    pl32_swap(v[1], v[3]);
+    pl16_swap(v[0], v[1]);
+    pl16_swap(v[2], v[3]);
+}
+
+template <bool COMP, bool TAB>
+__global__ __launch_bounds__(256) void k_zconv64(PassArg<ZDesc, TAB> A)
+{
+    constexpr int L = 64, CB = 16;
+    __shared__ float2 ex[3 * 4 * 4 * 4 * CB];  // [c][k0][k1][n0][col]
+    const ZDesc D = pass_desc(A);
+    const Geo &g = D.g;
+    int slot, kx, nst;
+    if constexpr (TAB) {
+        nst = (g.Py + CB - 1) / CB;
+        slot = (int)(blockIdx.x % nst);
+        kx = (int)(blockIdx.x / nst);
+    } else {
+        slot = blockIdx.x;
+        kx = blockIdx.y;
+        nst = gridDim.x;
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int col = lane & 15, r = lane >> 4;
+    const int t = 4 * r + w;
+    const int tile = zc_tile(slot, nst);
+    if (kx >= g.Hx || tile * CB >= g.Py) return;  // block-uniform, before any barrier
+    const int ky = tile * CB + col;
+    const bool ok = ky < g.Py;
+    const long long zs = g.Py;                           // stride between z
+    const long long cs = (long long)g.Hx * g.nz * g.Py;  // between components
+    float2 *__restrict__ base = D.S2 + (long long)kx * g.nz * g.Py + ky;
+    float2 v[3][4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int zz = t + 16 * q;
+            v[c][q] = (q < 2 && ok && zz < g.nz) ? base[c * cs + zz * zs] : make_float2(0.f, 0.f);
+        }
+    // twiddles W^(t j) and W^(4 w j), j = 1..3, and the octant entries of
+    // this thread's four frequencies, loaded with the data
+    float2 w1[4], w2[4];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+        w1[j] = twiddle<false>(t * j, L);
+        w2[j] = twiddle<false>(4 * w * j, L);
+    }
+    const bool fy = ky > g.Py / 2;
+    const int kyf = fy ? g.Py - ky : ky;
+    const float sy = fy ? -1.f : 1.f;
+    const float *kcol = D.K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
+    float2 kk[4][3];
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) zc_kload(kk[k2], kcol, ok, r + 4 * w + 16 * k2, g.Pz);
+    auto slot_at = [&](int c, int k0, int k1, int n0) { return (((c * 4 + k0) * 4 + k1) * 4 + n0) * CB + col; };
+    // forward
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Dft<4, false>::run(v[c]);
+#pragma unroll
+        for (int j = 1; j < 4; ++j) v[c][j] = cmul(v[c][j], w1[j]);
+        rows_transpose4(v[c]);
+        Dft<4, false>::run(v[c]);
+#pragma unroll
+        for (int j = 1; j < 4; ++j) v[c][j] = cmul(v[c][j], w2[j]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) ex[slot_at(c, r, k1, w)] = v[c][k1];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int n0 = 0; n0 < 4; ++n0) v[c][n0] = ex[slot_at(c, r, w, n0)];
+        Dft<4, false>::run(v[c]);
+    }
+    __syncthreads();  // every exchange read before the inverse writes
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) zc_apply<COMP>(v[0][k2], v[1][k2], v[2][k2], kk[k2], r + 4 * w + 16 * k2, g.Pz, sy);
+    // inverse
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        Dft<4, true>::run(v[c]);
+#pragma unroll
+        for (int j = 1; j < 4; ++j) v[c][j] = cmul(v[c][j], cconj(w2[j]));
+#pragma unroll
+        for (int n0 = 0; n0 < 4; ++n0) ex[slot_at(c, r, w, n0)] = v[c][n0];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) v[c][k1] = ex[slot_at(c, r, k1, w)];
+        Dft<4, true>::run(v[c]);
+        rows_transpose4(v[c]);
+#pragma unroll
+        for (int j = 1; j < 4; ++j) v[c][j] = cmul(v[c][j], cconj(w1[j]));
+        Dft<4, true>::run(v[c]);
+    }
+    if (ok) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int zz = t + 16 * q;
+                if (zz < g.nz) base[c * cs + zz * zs] = v[c][q];
+            }
+    }
+}
+
 // SEQ blocks of G > 1 tiles per 128-byte row: the G tiles of row group j
 // and the G tiles of its mirror group go to blocks 8 apart from each other
 // (one XCD, dispatched back to back), lower tiles first.  A bijection on
@@ -2109,6 +2253,8 @@ static void zc_launch(dim3 grid, const PassArg<ZDesc, TAB> &a, hipStream_t s)
     const size_t lds = S::LDS * sizeof(float2);
     if constexpr (S::SEQ)
         MMK_LAUNCH((k_zconv_seq<LL, COMP, VV, TAB>), grid, dim3(S::THREADS), lds, s, a);
+    else if constexpr (LL == 64 && VV == 0 && S::CB == 16 && S::THREADS == 256 && S::NSUB == 1)
+        MMK_LAUNCH((k_zconv64<COMP, TAB>), grid, dim3(256), 0, s, a);
     else
         MMK_LAUNCH((k_zconv<LL, COMP, VV, TAB>), grid, dim3(S::THREADS), lds, s, a);
 }
