@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel code whose hash
 # (kernel_source_sha) is recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv<64, false, 0, false>: FETCH_SIZE 76 676.4 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258089792,
-              "source_sha": "02c64c3d9e41417f2c0cfdff71b2350c3c627a4d3efbe17228ea866eddb5fca0"},
+    # k_zconv64<false, false>: FETCH_SIZE 76 672.3 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258081472,
+              "source_sha": "7ea1e20a6ef4b22beb6e521b671598f46deda5f36c436e5078a30ce549ba9cb9"},
 }
 
 def kernel_source_sha():
