@@ -671,7 +671,11 @@ template <bool COMP, bool TAB>
 __global__ __launch_bounds__(256) void k_zconv64(PassArg<ZDesc, TAB> A)
 {
     constexpr int L = 64, CB = 16;
-    __shared__ float2 ex[3 * 4 * 4 * 4 * CB];  // [c][k0][k1][n0][col]
+    // [c][k0][k1][n0][col]; each k0 block padded by one 128-byte row, so
+    // that the four lane rows of a wavefront (k0 = r, 2 KB apart unpadded)
+    // fall on different halves of the LDS banks
+    constexpr int K0S = 4 * 4 * CB + CB;
+    __shared__ float2 ex[3 * 4 * K0S];
     const ZDesc D = pass_desc(A);
     const Geo &g = D.g;
     int slot, kx, nst;
@@ -717,7 +721,7 @@ __global__ __launch_bounds__(256) void k_zconv64(PassArg<ZDesc, TAB> A)
     float2 kk[4][3];
 #pragma unroll
     for (int k2 = 0; k2 < 4; ++k2) zc_kload(kk[k2], kcol, ok, r + 4 * w + 16 * k2, g.Pz);
-    auto slot_at = [&](int c, int k0, int k1, int n0) { return (((c * 4 + k0) * 4 + k1) * 4 + n0) * CB + col; };
+    auto slot_at = [&](int c, int k0, int k1, int n0) { return (c * 4 + k0) * K0S + (k1 * 4 + n0) * CB + col; };
     // forward
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
