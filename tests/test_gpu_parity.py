@@ -71,6 +71,11 @@ GEOMS = [
     ((40, 24, 6), (3e-9, 4e-9, 5e-9)),     # anisotropic cells
     ((2, 512, 2), (5e-9, 2e-9, 5e-9)),     # longest y transform (1024 points)
     ((3, 2, 512), (5e-9, 5e-9, 1e-9)),     # longest z transform (1024 points)
+    # 64-point z transforms (the digit-split z pass): a column tile wider
+    # than Py, a ragged nz < Pz/2, and nz = Pz/2 exactly
+    ((5, 3, 20), (5e-9, 4e-9, 3e-9)),      # Py = 8: half the tile's columns beyond Py
+    ((6, 40, 17), (4e-9,) * 3),            # Py = 128, nz = 17
+    ((2, 9, 32), (3e-9, 5e-9, 2e-9)),      # Py = 32, nz = 32
 ]
 
 
