@@ -698,14 +698,24 @@ __global__ __launch_bounds__(256) void k_zconv64(PassArg<ZDesc, TAB> A)
     const long long zs = g.Py;                           // stride between z
     const long long cs = (long long)g.Hx * g.nz * g.Py;  // between components
     float2 *__restrict__ base = D.S2 + (long long)kx * g.nz * g.Py + ky;
+    // Every load is unconditional, so that each wait covers only what the
+    // code needs next (a load under a branch makes the compiler wait for
+    // all outstanding loads): points beyond nz read row 0 and are zeroed by
+    // a lane mask; a column beyond Py reads column 0, and as columns never
+    // mix and that column is not stored, its values do not matter.
+    const float2 *lbase = D.S2 + (long long)kx * g.nz * g.Py + (ok ? ky : 0);
     float2 v[3][4];
+    int mk[2];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+    for (int q = 0; q < 2; ++q) {
+        const int zz = t + 16 * q;
+        const bool in = zz < g.nz;
+        int zi = in ? zz : 0;
+        mk[q] = in ? -1 : 0;
+        asm volatile("" : "+v"(zi), "+v"(mk[q]));
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int zz = t + 16 * q;
-            v[c][q] = (q < 2 && ok && zz < g.nz) ? base[c * cs + zz * zs] : make_float2(0.f, 0.f);
-        }
+        for (int c = 0; c < 3; ++c) v[c][q] = lbase[c * cs + zi * zs];
+    }
     // twiddles W^(t j) and W^(4 w j), j = 1..3, and the octant entries of
     // this thread's four frequencies, loaded with the data
     float2 w1[4], w2[4];
@@ -717,10 +727,18 @@ __global__ __launch_bounds__(256) void k_zconv64(PassArg<ZDesc, TAB> A)
     const bool fy = ky > g.Py / 2;
     const int kyf = fy ? g.Py - ky : ky;
     const float sy = fy ? -1.f : 1.f;
-    const float *kcol = D.K + ((long long)kx * g.Hy + kyf) * g.Hz * 6;
+    const float *kcol = D.K + ((long long)kx * g.Hy + (ok ? kyf : 0)) * g.Hz * 6;
     float2 kk[4][3];
 #pragma unroll
-    for (int k2 = 0; k2 < 4; ++k2) zc_kload(kk[k2], kcol, ok, r + 4 * w + 16 * k2, g.Pz);
+    for (int k2 = 0; k2 < 4; ++k2) zc_kload(kk[k2], kcol, true, r + 4 * w + 16 * k2, g.Pz);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            v[c][q] = make_float2(__int_as_float(__float_as_int(v[c][q].x) & mk[q]),
+                                  __int_as_float(__float_as_int(v[c][q].y) & mk[q]));
+        v[c][2] = v[c][3] = make_float2(0.f, 0.f);
+    }
     auto slot_at = [&](int c, int k0, int k1, int n0) { return (c * 4 + k0) * K0S + (k1 * 4 + n0) * CB + col; };
     // forward
 #pragma unroll
