@@ -210,7 +210,9 @@ def cpu_full_steps():
 def adjoint_ratio(binding, T=2000):
     """Backward (segment replay + hand-written adjoint) over forward wall time
     of a T-step rollout on the 128x128x4 film, per-cell field and Ms maps,
-    L2 loss to the target pattern, sqrt(T) checkpoints."""
+    L2 loss to the target pattern, sqrt(T) checkpoints; then the same with
+    the whole trajectory stored by the forward (no replay; 2 T 3N floats of
+    device memory), reported beside it."""
     import torch
     from paper_1411_2565_amd import workloads
     from paper_1411_2565_amd.rollout import l2_loss, rollout
@@ -221,13 +223,13 @@ def adjoint_ratio(binding, T=2000):
     sim = binding.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, device=0)
     tgt = torch.tensor(t, **f32)
 
-    def once():
+    def once(store="checkpoint"):
         m0g = torch.tensor(m0, **f32).requires_grad_(True)
         hg = torch.tensor(h, **f32).requires_grad_(True)
         msg = torch.tensor(ms, **f32).requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        mT = rollout(m0g, hg, msg, sim, T, w.dt)
+        mT = rollout(m0g, hg, msg, sim, T, w.dt, 0, None, store)
         loss = l2_loss(mT, tgt, sim)  # FP64 reduction on the GPU
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -238,10 +240,14 @@ def adjoint_ratio(binding, T=2000):
 
     once()  # warm-up
     fwd, bwd = once()
+    once("all")
+    fwd_a, bwd_a = once("all")
     sim.close()
     return {"workload": "film 128x128x4, 5 nm cubes, T=2000, dt=1e-13, maps of h_ext and Ms, "
                         "checkpoint every 45 steps",
-            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "ratio": round(bwd / fwd, 3)}
+            "forward_s": round(fwd, 4), "backward_s": round(bwd, 4), "ratio": round(bwd / fwd, 3),
+            "stored": {"forward_s": round(fwd_a, 4), "backward_s": round(bwd_a, 4),
+                       "ratio": round(bwd_a / fwd_a, 3), "bytes": 2 * T * 3 * w.N * 4}}
 
 
 def batch_rate(binding, steps=5000, single_steps=200):

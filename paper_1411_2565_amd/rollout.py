@@ -6,14 +6,20 @@ the effective field of eq. (2)) on the GPU and returns m_T.  Its backward
 pass returns dL/dm0, dL/dh_ext (per-cell map, A/m) and dL/dMs (per-cell map)
 for any loss L(m_T), using the library's hand-written adjoint step.
 
-Memory: the forward keeps one state every S = ceil(sqrt(T)) steps.  The
-backward walks the segments from last to first; for each it replays the S
-forward steps from the checkpoint while storing every state and its
-demagnetising field (mm_forward_store), then runs the S adjoint steps
-backwards in one call (mm_adjoint_segment).  The replay computes the same
-arithmetic as the forward pass (whose Euler steps fuse the x-inverse and the
-update, bit for bit equal to the replay's two passes), so the recomputed
-states are bitwise those of the forward.
+Memory (``store``):
+- "checkpoint" (default): the forward keeps one state every S =
+  ceil(sqrt(T)) steps.  The backward walks the segments from last to first;
+  for each it replays the S forward steps from the checkpoint while storing
+  every state and its demagnetising field (mm_forward_store), then runs the
+  S adjoint steps backwards in one call (mm_adjoint_segment).  The replay
+  computes the same arithmetic as the forward pass (whose Euler steps fuse
+  the x-inverse and the update, bit for bit equal to the replay's two
+  passes), so the recomputed states are bitwise those of the forward.
+- "all": the forward itself stores every state and its demagnetising field
+  (2 T 3N floats of device memory) and the backward runs the T adjoint steps
+  alone, with no replay.  The same kernels in the same order as the
+  checkpointed form, so the same m_T and gradients bit for bit; it trades
+  memory (3.1 GB for a 128x128x4 film over 2000 steps) for the replay.
 """
 import math
 
@@ -28,19 +34,32 @@ def _segments(T, S):
 
 class LLGRollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None):
+    def forward(ctx, m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None, store="checkpoint"):
         T = int(T)
-        S = int(seg) if seg else max(1, math.ceil(math.sqrt(T)))
+        if store not in ("checkpoint", "all"):
+            raise ValueError(f"store must be 'checkpoint' or 'all', not {store!r}")
+        S = T if store == "all" else (int(seg) if seg else max(1, math.ceil(math.sqrt(T))))
         sim.set_hext_map(hext_map.detach().contiguous())
         sim.set_ms_map(ms_map.detach().contiguous())
         m = m0.detach().contiguous().clone()
+        ctx.sim, ctx.T, ctx.dt, ctx.flags, ctx.S = sim, T, dt, flags, S
+        ctx.maps = (hext_map.detach().contiguous(), ms_map.detach().contiguous())
+        ctx.traj = None
+        if store == "all":
+            N = sim.N
+            mtraj = torch.empty((max(T, 1), 3 * N), dtype=torch.float32, device=m.device)
+            hdtraj = torch.empty_like(mtraj)
+            if T:
+                sim._s()
+                B.mm_forward_store(sim.ctx, m, T, dt, flags, mtraj[:T], hdtraj[:T], N)
+            ctx.traj = (mtraj, hdtraj)
+            ctx.ckpts = None
+            return m
         ckpts = []
         for (_, n) in _segments(T, S):
             ckpts.append(m.clone())
             sim.step(m, n, dt, flags)
-        ctx.sim, ctx.T, ctx.dt, ctx.flags, ctx.S = sim, T, dt, flags, S
         ctx.ckpts = ckpts
-        ctx.maps = (hext_map.detach().contiguous(), ms_map.detach().contiguous())
         return m
 
     @staticmethod
@@ -53,6 +72,13 @@ class LLGRollout(torch.autograd.Function):
         g_h = torch.zeros_like(hmap)
         g_ms = torch.zeros_like(msmap)
         N = sim.N
+        if ctx.traj is not None:  # store == "all": no replay
+            mtraj, hdtraj = ctx.traj
+            if T:
+                sim._s()
+                B.mm_adjoint_segment(sim.ctx, mtraj[:T], hdtraj[:T], T, lam, g_h, g_ms, dt, flags, N)
+            ctx.traj = None
+            return lam, g_h, g_ms, None, None, None, None, None, None
         segs = _segments(T, S)
         mtraj = torch.empty((S, 3 * N), dtype=torch.float32, device=lam.device)
         hdtraj = torch.empty_like(mtraj)
@@ -63,12 +89,13 @@ class LLGRollout(torch.autograd.Function):
             B.mm_forward_store(sim.ctx, m, n, dt, flags, mtraj[:n], hdtraj[:n], N)
             B.mm_adjoint_segment(sim.ctx, mtraj[:n], hdtraj[:n], n, lam, g_h, g_ms, dt, flags, N)
         ctx.ckpts = None
-        return lam, g_h, g_ms, None, None, None, None, None
+        return lam, g_h, g_ms, None, None, None, None, None, None
 
 
-def rollout(m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None):
-    """m_T of a T-step Euler rollout, differentiable in m0, hext_map, ms_map."""
-    return LLGRollout.apply(m0, hext_map, ms_map, sim, T, dt, flags, seg)
+def rollout(m0, hext_map, ms_map, sim, T, dt, flags=0, seg=None, store="checkpoint"):
+    """m_T of a T-step Euler rollout, differentiable in m0, hext_map, ms_map;
+    store = "checkpoint" (sqrt(T) checkpoints, default) or "all"."""
+    return LLGRollout.apply(m0, hext_map, ms_map, sim, T, dt, flags, seg, store)
 
 
 class L2Loss(torch.autograd.Function):

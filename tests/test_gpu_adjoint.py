@@ -46,18 +46,20 @@ def film_analogue(n=(32, 32, 4)):
     return w, m0, ms, h, t
 
 
-def gpu_grads(gpu_lib, w, m0, ms, h, t, T, dt, seg=None, Ku=0.0, u=(1.0, 0.0, 0.0)):
+def gpu_grads(gpu_lib, w, m0, ms, h, t, T, dt, seg=None, Ku=0.0, u=(1.0, 0.0, 0.0), store="checkpoint",
+              with_mT=False):
     import torch
     from paper_1411_2565_amd.rollout import l2_loss, rollout
     sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, Ku=Ku, u=u, alpha=w.alpha)
     m0g = gpu(m0).requires_grad_(True)
     hg = gpu(h).requires_grad_(True)
     msg = gpu(ms).requires_grad_(True)
-    mT = rollout(m0g, hg, msg, sim, T, dt, 0, seg)
+    mT = rollout(m0g, hg, msg, sim, T, dt, 0, seg, store)
     loss = l2_loss(mT, gpu(t), sim)
     loss.backward()
     torch.cuda.synchronize()
-    return float(loss.detach()), host(m0g.grad), host(hg.grad), host(msg.grad), sim
+    out = (float(loss.detach()), host(m0g.grad), host(hg.grad), host(msg.grad), sim)
+    return out + (host(mT),) if with_mT else out
 
 
 @pytest.mark.parametrize("Ku", [0.0, 4e4])
@@ -86,6 +88,27 @@ def test_checkpointing_is_exact(gpu_lib):
     b = gpu_grads(gpu_lib, w, m0, ms, h, t, 37, 2e-14, seg=37)
     for x, y in zip(a[1:4], b[1:4]):
         np.testing.assert_array_equal(x, y)
+
+
+def test_stored_trajectory_equals_checkpointing(gpu_lib):
+    """store="all" (the forward stores every state and field, no replay)
+    gives the checkpointed rollout's m_T, loss and gradients bit for bit."""
+    w, m0, ms, h, t = film_analogue((32, 32, 4))
+    a = gpu_grads(gpu_lib, w, m0, ms, h, t, 100, 2e-14, with_mT=True)
+    b = gpu_grads(gpu_lib, w, m0, ms, h, t, 100, 2e-14, store="all", with_mT=True)
+    assert a[0] == b[0]
+    for x, y in zip(a[1:4] + a[5:], b[1:4] + b[5:]):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_rollout_rejects_unknown_store(gpu_lib):
+    import torch
+    from paper_1411_2565_amd.rollout import rollout
+    w, m0, ms, h, t = film_analogue((8, 8, 2))
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha)
+    with pytest.raises(ValueError):
+        rollout(gpu(m0), gpu(h), gpu(ms), sim, 3, 2e-14, 0, None, "some")
+    torch.cuda.synchronize()
 
 
 def test_adjoint_segment_equals_single_steps(gpu_lib):
