@@ -31,9 +31,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # size), keyed by kernel; valid only for the kernel code whose hash
 # (kernel_source_sha) is recorded with them.  The summaries and commands are in profiles/.
 MEASURED_TRAFFIC = {
-    # k_zconv64<false, false>: FETCH_SIZE 76 672.4 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
-    "zconv": {"bytes_per_launch": 258081600,
-              "source_sha": "e7db150bdebb2756e27866981f2793b40b274898b943226d3951561dac6791d7"},
+    # k_zconv64<false, false>: FETCH_SIZE 76 697.4 KiB x 2.0 + WRITE_SIZE 98 688.0 KiB
+    "zconv": {"bytes_per_launch": 258132736,
+              "source_sha": "8f130732107ed39672f024651b8380b26c65f6e1a486dc707f7be6fcae7987ea"},
 }
 
 def kernel_source_sha():

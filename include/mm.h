@@ -173,6 +173,16 @@ mm_status mm_build_tensor(mm_ctx *c);
  * into tab_dev (6N doubles, device).  Synchronous. */
 mm_status mm_tensor_table(mm_ctx *c, double *tab_dev);
 
+/* Diagnostic of the spectral multiply's arithmetic (each component of
+ * H(k) = K(k) M(k), Sec. 3, is a dot product of three terms): for the n
+ * triples (k0, x0, k1, x1, k2, x2) at in_dev[6 i] (6n floats, device),
+ * writes out_dev[2 i] = k0 x0 + k1 x1 + k2 x2 as the plain multiply
+ * computes it and out_dev[2 i + 1] as the compensated one (MM_F_COMPENSATED,
+ * Dot2 of Ogita, Rump and Oishi) does, with the same device functions as
+ * the z passes (2n floats, device).  0 <= n <= 2^31 (MM_EINVAL otherwise);
+ * n = 0 does nothing.  Needs no workspace; synchronous. */
+mm_status mm_diag_dot3(mm_ctx *c, const float *in_dev, float *out_dev, int64_t n);
+
 /* Effective field of eq. (2) restricted to the terms in `terms`
  * (MM_T_* mask) for the state m_dev, written to h_dev (3N floats, A/m,
  * may not alias m_dev).  MM_T_DEMAG requires mm_build_tensor. */

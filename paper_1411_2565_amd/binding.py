@@ -63,6 +63,7 @@ def load():
         "mm_set_hext_map": [_P, _P],
         "mm_build_tensor": [_P],
         "mm_tensor_table": [_P, _P],
+        "mm_diag_dot3": [_P, _P, _P, ctypes.c_int64],
         "mm_compute_heff": [_P, _P, _P, ctypes.c_uint32],
         "mm_step_llg": [_P, _P, ctypes.c_int64, ctypes.c_double, ctypes.c_uint32],
         "mm_reduce": [_P, _P, _P],
@@ -200,6 +201,15 @@ def mm_build_tensor(ctx):
 def mm_tensor_table(ctx, out, N):
     import torch
     _check(ctx, load().mm_tensor_table(ctx, _dev(out, torch.float64, 6 * N, "table")), "mm_tensor_table")
+
+
+def mm_diag_dot3(ctx, inp, out, n):
+    """Plain and compensated three-term dot products of n triples (6n floats
+    in, 2n floats out), as the spectral multiply computes them."""
+    import torch
+    n = int(n)
+    _check(ctx, load().mm_diag_dot3(ctx, _dev(inp, torch.float32, 6 * n, "in") if n else None,
+                                    _dev(out, torch.float32, 2 * n, "out") if n else None, n), "mm_diag_dot3")
 
 
 def mm_compute_heff(ctx, m, h, terms, N):

@@ -538,6 +538,17 @@ mm_status mm_tensor_table(mm_ctx *c, double *tab)
     return hipcheck(c, hipStreamSynchronize(c->stream), "tensor table sync");
 }
 
+mm_status mm_diag_dot3(mm_ctx *c, const float *in, float *out, int64_t n)
+{
+    if (!c) return MM_EINVAL;
+    if (n < 0 || n > ((int64_t)1 << 31)) return fail(c, MM_EINVAL, "n must be in [0, 2^31]");
+    if (n == 0) return MM_OK;
+    if (!in || !out) return fail(c, MM_EINVAL, "in and out must be non-NULL");
+    MM_TRY(set_device(c));
+    MM_TRY(hipcheck(c, mmk::launch_diag_dot3(in, out, n, c->stream), "dot3 diagnostic"));
+    return hipcheck(c, hipStreamSynchronize(c->stream), "dot3 diagnostic sync");
+}
+
 mm_status mm_build_tensor(mm_ctx *c)
 {
     if (!c) return MM_EINVAL;

@@ -473,6 +473,24 @@ __device__ __forceinline__ float dot3_comp(float k0, float x0, float k1, float x
     return q + s;
 }
 
+// The plain form: two fmas and a product, rounded three times.
+__device__ __forceinline__ float dot3_plain(float k0, float x0, float k1, float x1, float k2, float x2)
+{
+    return fmaf(k0, x0, fmaf(k1, x1, k2 * x2));
+}
+
+// Diagnostic of the multiply's two forms on n triples (k0, x0, k1, x1, k2,
+// x2) at in[6 i]: out[2 i] the plain form, out[2 i + 1] the compensated one.
+__global__ __launch_bounds__(kThreads) void k_diag_dot3(const float *__restrict__ in, float *__restrict__ out,
+                                                        long long n)
+{
+    const long long i = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float *a = in + 6 * i;
+    out[2 * i] = dot3_plain(a[0], a[1], a[2], a[3], a[4], a[5]);
+    out[2 * i + 1] = dot3_comp(a[0], a[1], a[2], a[3], a[4], a[5]);
+}
+
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // ky tiles are ordered so that a tile and its mirror tile (whose columns use
 // the same octant rows of K) are 8 blocks apart, i.e. on the same XCD.
@@ -513,9 +531,9 @@ __device__ __forceinline__ void zc_apply(float2 &mx, float2 &my, float2 &mz, con
         my = make_float2(dot3_comp(kxy, ax.x, kyy, ay.x, kyz, az.x), dot3_comp(kxy, ax.y, kyy, ay.y, kyz, az.y));
         mz = make_float2(dot3_comp(kxz, ax.x, kyz, ay.x, kzz, az.x), dot3_comp(kxz, ax.y, kyz, ay.y, kzz, az.y));
     } else {
-        mx = make_float2(fmaf(kxx, ax.x, fmaf(kxy, ay.x, kxz * az.x)), fmaf(kxx, ax.y, fmaf(kxy, ay.y, kxz * az.y)));
-        my = make_float2(fmaf(kxy, ax.x, fmaf(kyy, ay.x, kyz * az.x)), fmaf(kxy, ax.y, fmaf(kyy, ay.y, kyz * az.y)));
-        mz = make_float2(fmaf(kxz, ax.x, fmaf(kyz, ay.x, kzz * az.x)), fmaf(kxz, ax.y, fmaf(kyz, ay.y, kzz * az.y)));
+        mx = make_float2(dot3_plain(kxx, ax.x, kxy, ay.x, kxz, az.x), dot3_plain(kxx, ax.y, kxy, ay.y, kxz, az.y));
+        my = make_float2(dot3_plain(kxy, ax.x, kyy, ay.x, kyz, az.x), dot3_plain(kxy, ax.y, kyy, ay.y, kyz, az.y));
+        mz = make_float2(dot3_plain(kxz, ax.x, kyz, ay.x, kzz, az.x), dot3_plain(kxz, ax.y, kyz, ay.y, kzz, az.y));
     }
 }
 
@@ -545,9 +563,9 @@ __device__ __forceinline__ void zc_point(float2 &mx, float2 &my, float2 &mz, con
         my = make_float2(dot3_comp(kxy, ax.x, kyy, ay.x, kyz, az.x), dot3_comp(kxy, ax.y, kyy, ay.y, kyz, az.y));
         mz = make_float2(dot3_comp(kxz, ax.x, kyz, ay.x, kzz, az.x), dot3_comp(kxz, ax.y, kyz, ay.y, kzz, az.y));
     } else {
-        mx = make_float2(fmaf(kxx, ax.x, fmaf(kxy, ay.x, kxz * az.x)), fmaf(kxx, ax.y, fmaf(kxy, ay.y, kxz * az.y)));
-        my = make_float2(fmaf(kxy, ax.x, fmaf(kyy, ay.x, kyz * az.x)), fmaf(kxy, ax.y, fmaf(kyy, ay.y, kyz * az.y)));
-        mz = make_float2(fmaf(kxz, ax.x, fmaf(kyz, ay.x, kzz * az.x)), fmaf(kxz, ax.y, fmaf(kyz, ay.y, kzz * az.y)));
+        mx = make_float2(dot3_plain(kxx, ax.x, kxy, ay.x, kxz, az.x), dot3_plain(kxx, ax.y, kxy, ay.y, kxz, az.y));
+        my = make_float2(dot3_plain(kxy, ax.x, kyy, ay.x, kyz, az.x), dot3_plain(kxy, ax.y, kyy, ay.y, kyz, az.y));
+        mz = make_float2(dot3_plain(kxz, ax.x, kyz, ay.x, kzz, az.x), dot3_plain(kxz, ax.y, kyz, ay.y, kzz, az.y));
     }
 }
 
@@ -2762,6 +2780,14 @@ hipError_t launch_errmax(const float *e, long long n, unsigned *out, hipStream_t
     long long blocks = (n + kThreads - 1) / kThreads;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_errmax, dim3((unsigned)blocks), dim3(kThreads), 0, s, e, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_dot3(const float *in, float *out, long long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag_dot3, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, in, out,
+                       n);
     return hipGetLastError();
 }
 

@@ -212,6 +212,7 @@ hipError_t launch_stage(const Geo &g, const LocalParams &p, const float *m, cons
 // out (one unsigned, zeroed by the caller) <- bits of max(e[0..n)) for e >= 0
 // or NaN (NaN wins: its bit pattern orders above every finite value)
 hipError_t launch_errmax(const float *e, long long n, unsigned *out, hipStream_t s);
+hipError_t launch_diag_dot3(const float *in, float *out, long long n, hipStream_t s);
 // out[0] |= 1 if a value of v[0..n) is negative or not finite, out[1] |= 1
 // if a value is zero (out zeroed by the caller)
 hipError_t launch_map_check(const float *v, long long n, unsigned *out, hipStream_t s);
