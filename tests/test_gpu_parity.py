@@ -413,20 +413,6 @@ def test_compensated_multiply_error_vs_oracle(gpu_lib, n, d, seed):
     assert errs[(1, 2)] < 1.5 * errs[(0, 2)]
 
 
-def cancelling_triples(n, seed):
-    """n float32 triples (k0, x0, k1, x1, k2, x2) whose dot product cancels:
-    x2 is chosen so that k2 x2 undoes k0 x0 + k1 x1 up to a relative 1e-7 ...
-    1e-2, i.e. condition numbers from about 1e2 to beyond 1/u."""
-    rng = np.random.default_rng(seed)
-    sgn = lambda size: rng.choice([-1.0, 1.0], size)  # noqa: E731
-    k = (rng.uniform(0.1, 10.0, (n, 3)) * sgn((n, 3))).astype(np.float32)
-    x = (rng.uniform(0.1, 10.0, (n, 3)) * sgn((n, 3))).astype(np.float32)
-    delta = 10.0 ** rng.uniform(-7, -2, n) * sgn(n)
-    part = k[:, 0].astype(np.float64) * x[:, 0] + k[:, 1].astype(np.float64) * x[:, 1]
-    x[:, 2] = (-part / k[:, 2] * (1.0 + delta)).astype(np.float32)
-    return np.stack([k[:, 0], x[:, 0], k[:, 1], x[:, 1], k[:, 2], x[:, 2]], axis=1)
-
-
 def test_compensated_dot_is_twice_the_working_precision(gpu_lib):
     """The compensated multiply's three-term dot product (Dot2, Ogita, Rump
     and Oishi 2005) against the exact rational value of the same float
@@ -440,7 +426,7 @@ def test_compensated_dot_is_twice_the_working_precision(gpu_lib):
     own error (the FP32 transforms and tensor spectrum carry errors of the
     same size)."""
     import torch
-    from fractions import Fraction
+    from tests.dot2_check import U, cancelling_triples, judge
     n = 4096
     trip = cancelling_triples(n, 3)
     sim = gpu_lib.Sim((8, 8, 2), (5e-9,) * 3, Ms=8.6e5, A=1.3e-11, alpha=0.1)
@@ -448,20 +434,8 @@ def test_compensated_dot_is_twice_the_working_precision(gpu_lib):
     out = torch.empty(2 * n, dtype=torch.float32, device="cuda:0")
     gpu_lib.mm_diag_dot3(sim.ctx, inp, out, n)
     res = out.cpu().numpy().reshape(n, 2).astype(np.float64)
-    u = 2.0 ** -24
-    g3 = 3 * u / (1 - 3 * u)
-    worst, plain_rel, conds = 0.0, [], []
-    for i in range(n):
-        a = [Fraction(float(v)) for v in trip[i]]
-        s = a[0] * a[1] + a[2] * a[3] + a[4] * a[5]
-        absum = abs(a[0] * a[1]) + abs(a[2] * a[3]) + abs(a[4] * a[5])
-        err_c = abs(Fraction(res[i, 1]) - s)
-        bound = u * abs(s) + g3 * g3 * absum
-        worst = max(worst, float(err_c / bound) if bound else float(err_c > 0))
-        if s != 0:
-            conds.append(float(absum / abs(s)))
-            plain_rel.append(float(abs(Fraction(res[i, 0]) - s) / abs(s)))
-    conds, plain_rel = np.array(conds), np.array(plain_rel)
+    worst, conds, plain_rel = judge(trip, res[:, 1], res[:, 0])
+    u = U
     hi = conds > 1e4
     print(f"Dot2 diagnostic: {n} triples, condition numbers {conds.min():.1e} .. {conds.max():.1e}; "
           f"compensated error / bound max {worst:.3f}; plain relative error median {np.median(plain_rel[hi]):.2e} "
