@@ -595,7 +595,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the single-GPU throughput is the --gpus 1 line)", file=sys.stderr)
         sys.exit(2)
 

@@ -50,7 +50,7 @@ typedef enum {
     MM_ESTATE = -2,      /* call out of order (no workspace, material or tensor) */
     MM_ENOMEM = -3,      /* workspace too small */
     MM_EHIP = -4,        /* a HIP runtime call failed */
-    MM_EUNSUP = -5,      /* supported by the method but not by this build */
+    MM_EUNSUP = -5,      /* supported by the method but not by this library */
     MM_ENONFINITE = -6   /* a step produced a non-finite magnetisation */
 } mm_status;
 

@@ -1,6 +1,6 @@
 """Compile the FP64 oracle (plain C) into a shared library next to its source.
 
-Test infrastructure: the product build step compiles it too, so the checker
+Test infrastructure: the product build step compiles it too, so the oracle
 exists wherever the tests run; nothing in the product path loads it.
 """
 import os

@@ -5,7 +5,7 @@ product with Dot2 (Ogita, Rump and Oishi, "Accurate sum and dot product",
 SIAM J. Sci. Comput. 26 (2005)), whose result res satisfies
 |res - s| <= u |s| + gamma_n^2 sum |k_i x_i| for the exact value s of the same
 float inputs (u = 2^-24 for binary32, gamma_n = n u / (1 - n u), n = 3 here).
-`judge` measures results against that bound with exact rational arithmetic.
+`against_bound` measures results against that bound with exact rational arithmetic.
 """
 from fractions import Fraction
 
@@ -32,7 +32,7 @@ def cancelling_triples(n, seed):
     return np.stack([k[:, 0], x[:, 0], k[:, 1], x[:, 1], k[:, 2], x[:, 2]], axis=1)
 
 
-def judge(trip, comp, plain):
+def against_bound(trip, comp, plain):
     """Largest ratio of the compensated results' error to Dot2's bound, and,
     over the triples whose exact value is not zero, the condition numbers
     sum |k_i x_i| / |s| and the plain results' relative errors."""

@@ -12,7 +12,7 @@ from fractions import Fraction
 
 import numpy as np
 
-from tests.dot2_check import U, cancelling_triples, judge
+from tests.dot2_check import U, cancelling_triples, against_bound
 
 f = np.float32
 
@@ -56,8 +56,8 @@ def test_criterion_separates_dot2_from_contracted_dot2():
     good = np.array([dot2(*t) for t in trip])
     bad = np.array([dot2(*t, contract=True) for t in trip])
     pl = np.array([plain(*t) for t in trip])
-    worst_good, conds, plain_rel = judge(trip, good, pl)
-    worst_bad, _, _ = judge(trip, bad, pl)
+    worst_good, conds, plain_rel = against_bound(trip, good, pl)
+    worst_bad, _, _ = against_bound(trip, bad, pl)
     hi = conds > 1e4
     assert worst_good <= 1.0
     assert worst_bad > 100.0

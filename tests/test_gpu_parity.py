@@ -426,7 +426,7 @@ def test_compensated_dot_is_twice_the_working_precision(gpu_lib):
     own error (the FP32 transforms and tensor spectrum carry errors of the
     same size)."""
     import torch
-    from tests.dot2_check import U, cancelling_triples, judge
+    from tests.dot2_check import U, cancelling_triples, against_bound
     n = 4096
     trip = cancelling_triples(n, 3)
     sim = gpu_lib.Sim((8, 8, 2), (5e-9,) * 3, Ms=8.6e5, A=1.3e-11, alpha=0.1)
@@ -434,7 +434,7 @@ def test_compensated_dot_is_twice_the_working_precision(gpu_lib):
     out = torch.empty(2 * n, dtype=torch.float32, device="cuda:0")
     gpu_lib.mm_diag_dot3(sim.ctx, inp, out, n)
     res = out.cpu().numpy().reshape(n, 2).astype(np.float64)
-    worst, conds, plain_rel = judge(trip, res[:, 1], res[:, 0])
+    worst, conds, plain_rel = against_bound(trip, res[:, 1], res[:, 0])
     u = U
     hi = conds > 1e4
     print(f"Dot2 diagnostic: {n} triples, condition numbers {conds.min():.1e} .. {conds.max():.1e}; "
