@@ -59,6 +59,7 @@ def test_null_arguments_rejected():
     assert lib.mm_destroy(None) == binding.MM_EINVAL
     assert lib.mm_sync(None) == binding.MM_EINVAL
     assert lib.mm_step_llg(None, None, 1, 1e-13, 0) == binding.MM_EINVAL
+    assert lib.mm_diag_dot3(None, None, None, 1) == binding.MM_EINVAL
 
 
 def test_product_path_does_not_import_oracle():

@@ -427,9 +427,12 @@ def test_compensated_dot_is_twice_the_working_precision(gpu_lib):
     same size)."""
     import torch
     from tests.dot2_check import U, cancelling_triples, against_bound
-    n = 4096
+    n = 4096 + 77  # a ragged last block
     trip = cancelling_triples(n, 3)
     sim = gpu_lib.Sim((8, 8, 2), (5e-9,) * 3, Ms=8.6e5, A=1.3e-11, alpha=0.1)
+    lib = gpu_lib.load()
+    assert lib.mm_diag_dot3(sim.ctx, None, None, -1) == gpu_lib.MM_EINVAL
+    assert lib.mm_diag_dot3(sim.ctx, None, None, 0) == gpu_lib.MM_OK
     inp = torch.tensor(trip.reshape(-1), dtype=torch.float32, device="cuda:0")
     out = torch.empty(2 * n, dtype=torch.float32, device="cuda:0")
     gpu_lib.mm_diag_dot3(sim.ctx, inp, out, n)
