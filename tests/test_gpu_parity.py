@@ -354,6 +354,33 @@ def test_invalid_arguments(gpu_lib):
     assert ei.value.code == b.MM_EINVAL
 
 
+def test_zero_and_odd_step_counts(gpu_lib):
+    """nsteps = 0 leaves the state as it is, eager and with MM_F_GRAPH;
+    nsteps < 0 is rejected; odd counts with MM_F_GRAPH (a captured even chunk
+    and an eager tail, or no chunk at all) equal eager stepping bit for bit."""
+    import torch
+    w, m0, args = _block16()
+    s = torch.cuda.Stream()  # graph capture needs a stream of its own
+    with torch.cuda.stream(s):
+        sim = gpu_lib.Sim(w.n, w.d, **args)
+        m = gpu(m0)
+        ref = m.clone()
+        for flags in (0, gpu_lib.MM_F_GRAPH):
+            sim.step(m, 0, w.dt, flags)
+            sim.sync()
+            assert torch.equal(m, ref)
+        with pytest.raises(gpu_lib.MMError) as ei:
+            gpu_lib.mm_step_llg(sim.ctx, m, -1, w.dt, 0, sim.N)
+        assert ei.value.code == gpu_lib.MM_EINVAL
+        for n in (1, 3, 35):
+            a, b = gpu(m0), gpu(m0)
+            sim.step(a, n, w.dt)
+            sim.step(b, n, w.dt, gpu_lib.MM_F_GRAPH)
+            sim.sync()
+            assert torch.equal(a, b), n
+        sim.close()
+
+
 def test_nonfinite_state_is_reported(gpu_lib):
     import torch
     b = gpu_lib
