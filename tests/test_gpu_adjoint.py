@@ -101,6 +101,25 @@ def test_stored_trajectory_equals_checkpointing(gpu_lib):
         np.testing.assert_array_equal(x, y)
 
 
+def test_rollout_degenerate_horizons(gpu_lib):
+    """T = 0: m_T is m0, dL/dm0 is dL/dm_T = m0 - t and the map gradients are
+    zero, in both storage modes; T = 1: one adjoint step, the two modes bit
+    for bit equal."""
+    w, m0, ms, h, t = film_analogue((8, 8, 2))
+    m0f = host(gpu(m0)).astype(np.float32)
+    tf = host(gpu(t)).astype(np.float32)
+    for store in ("checkpoint", "all"):
+        loss, gm, gh, gms, _, mT = gpu_grads(gpu_lib, w, m0, ms, h, t, 0, 2e-14, store=store, with_mT=True)
+        np.testing.assert_array_equal(mT, m0f)
+        np.testing.assert_array_equal(gm, (m0f - tf).astype(np.float64))
+        assert not gh.any() and not gms.any()
+    a = gpu_grads(gpu_lib, w, m0, ms, h, t, 1, 2e-14, with_mT=True)
+    b = gpu_grads(gpu_lib, w, m0, ms, h, t, 1, 2e-14, store="all", with_mT=True)
+    assert a[0] == b[0]
+    for x, y in zip(a[1:4] + a[5:], b[1:4] + b[5:]):
+        np.testing.assert_array_equal(x, y)
+
+
 def test_rollout_rejects_unknown_store(gpu_lib):
     import torch
     from paper_1411_2565_amd.rollout import rollout
