@@ -63,6 +63,35 @@ def test_batch_members_match_single_runs(gpu_lib, films):
     B.close()
 
 
+def test_batch_of_one_and_zero_steps(gpu_lib, films):
+    """A batch of a single film: nsteps = 0 leaves the packed state as it is,
+    nsteps < 0 is rejected, and 100 steps match the film's single run (within
+    1e-6: the batch builds the spectrum for the padded size's largest
+    extent, the single run for the film's own)."""
+    import torch
+    w, m0, h = films[0]
+    B = gpu_lib.Batch([w.n], w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=[tuple(h)])
+    m = B.pack([m0])
+    ref = m.clone()
+    B.step(m, 0, w.dt)
+    B.sync()
+    assert torch.equal(m, ref)
+    with pytest.raises(gpu_lib.MMError) as ei:
+        B.step(m, -1, w.dt)
+    assert ei.value.code == gpu_lib.MM_EINVAL
+    B.step(m, 100, w.dt)
+    B.sync()
+    sim = gpu_lib.Sim(w.n, w.d, Ms=w.Ms, A=w.A, alpha=w.alpha, hext=tuple(h))
+    ms = torch.tensor(m0, dtype=torch.float32, device="cuda:0")
+    sim.step(ms, 100, w.dt)
+    sim.sync()
+    e = rel(host(B.unpack(m, 0)), host(ms))
+    print(f"batch of one {w.n} vs its single run after 100 steps: rel L2 {e:.2e}")
+    assert e < 1e-6
+    sim.close()
+    B.close()
+
+
 def test_batch_graph_equals_eager(gpu_lib, films):
     import torch
     w0 = films[0][0]
